@@ -1,0 +1,167 @@
+/*
+ * jacobi.h -- C ABI of the MI355X (gfx950) Jacobi library, libjacobi.so.
+ *
+ * The method: repeated sweeps of the 3D Jacobi update (update equation of
+ * Sect. 1.1 of Wittmann, Hager, Wellein, "Multicore-aware parallel temporal
+ * blocking of stencil codes for shared and distributed memory"):
+ *     B(i,j,k) = ( A(i-1,j,k) + A(i+1,j,k) + A(i,j-1,k) + A(i,j+1,k)
+ *                + A(i,j,k-1) + A(i,j,k+1) ) / 6
+ * over the interior of a grid whose one-cell shell holds fixed Dirichlet data,
+ * writing grids A and B in turn (same section).  Temporal blocking (the idea
+ * of Sect. 1.1, the shrinking-overlap rule of Sect. 2.1) fuses t sweeps into
+ * one pass over device memory.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Buffers are DEVICE pointers owned by the caller.  The library never
+ *    allocates, frees or retains them.  Host pointers are named as such.
+ *  - Element (i,j,k), 0 <= i <= nx+1, 0 <= j <= ny+1, 0 <= k <= nz+1, of a grid
+ *    lives at base[i + j*sy + k*sz]: i is contiguous.  Index 0 and n+1 on any
+ *    axis is the Dirichlet shell, which no call writes (except where stated).
+ *    Only the six face layers of the shell are ever read; the 12 edges and 8
+ *    corners of the shell are never read.
+ *  - dtype: JAC_F32 (float) or JAC_F64 (double); all grids of a call share it.
+ *  - Arithmetic: FP64 sums the six neighbours left to right in the printed
+ *    order (i-1, i+1, j-1, j+1, k-1, k+1) and divides by 6 with a correctly
+ *    rounded division, so every FP64 result is bitwise the plain sequential
+ *    result, whatever the blocking depth, tile or pass split.  FP32 sums in
+ *    the same order and multiplies by the float nearest 1/6.
+ *  - Calls enqueue work on `stream` (a hipStream_t; NULL = the null stream)
+ *    and return without synchronising.  Argument checks happen before any
+ *    HIP call and are synchronous: a failed check returns JAC_EARG and
+ *    enqueues nothing.  JAC_EHIP reports an error the HIP runtime returned
+ *    while enqueuing; faults inside kernels surface at the caller's next
+ *    synchronisation.  jacobi_last_error() describes the last failure of the
+ *    calling thread.  No exception crosses the ABI.
+ *  - Ping-pong results: `a` holds level 0 on entry.  The library copies a's
+ *    shell into b (O(N^2) work) and ignores b's other contents.  On return
+ *    *out_idx says where the result is: 0 = a, 1 = b.  It equals the number
+ *    of passes over memory modulo 2 (one pass per sweep for jacobi_plain,
+ *    so there out_idx = T mod 2).  The other buffer holds an intermediate
+ *    level.
+ *  - Thread safety: calls are independent; concurrent calls on different
+ *    buffers are safe.
+ */
+#ifndef JACOBI_H
+#define JACOBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JACOBI_ABI_VERSION 1
+
+/* Grid geometry.  nx, ny, nz >= 1 are the interior extents.  sy and sz are the
+ * element strides of j and k; 0 selects the dense strides sy = nx+2 and
+ * sz = sy*(ny+2).  Non-zero strides must satisfy sy >= nx+2, sz >= sy*(ny+2). */
+typedef struct jac_grid {
+    int64_t nx, ny, nz;
+    int64_t sy, sz;
+} jac_grid_t;
+
+/* Blocking parameters of one temporally blocked call.
+ *   t      sweeps fused per pass over memory, 1..JAC_MAX_DEPTH (0 = library
+ *          choice).  T sweeps take ceil(T/t) passes; the depths of the passes
+ *          differ by at most one.
+ *   bx, by i- and j-extent of the block of cells one workgroup updates at every
+ *          level, recomputed halo included (the valid part shrinks by one
+ *          cell per side and level, Sect. 2.1).  Supported pairs are listed by
+ *          jacobi_tile_menu(); 0 = library choice.
+ *   kchunk planes of output per workgroup along k (the k range is split so
+ *          that the chip has enough workgroups); 0 = library choice. */
+typedef struct jac_tile {
+    int32_t t, bx, by, kchunk;
+} jac_tile_t;
+
+#define JAC_MAX_DEPTH 8
+
+enum { JAC_F32 = 0, JAC_F64 = 1 };
+enum {
+    JAC_OK = 0,
+    JAC_EARG = -1,         /* invalid argument (see jacobi_last_error) */
+    JAC_EHIP = -2,         /* the HIP runtime returned an error */
+    JAC_EWORKSPACE = -3,   /* workspace missing or too small */
+    JAC_EUNSUPPORTED = -4  /* valid request this build has no kernel for */
+};
+
+/* Library version (JACOBI_ABI_VERSION of the build). */
+int jacobi_version(void);
+
+/* Description of the last failure on the calling thread ("" if none).  The
+ * string stays valid until the thread's next call into the library. */
+const char *jacobi_last_error(void);
+
+/* T plain sweeps, one pass over memory per sweep (the standard Jacobi
+ * iteration of Sect. 1.1, whose memory-bound rate Eq. 2 models).
+ * a: level 0 on entry; b: second grid of the pair.  T >= 0 (T = 0: nothing is
+ * enqueued, *out_idx = 0). */
+int jacobi_plain(int dtype, const jac_grid_t *g, void *a, void *b, int T,
+                 void *stream, int *out_idx);
+
+/* T sweeps fused t at a time (temporal blocking, Sect. 1.1; overlapped tiles
+ * whose update s covers a region one layer wider per remaining level,
+ * Sect. 2.1).  tile == NULL or zero fields: library choice.
+ * rhs == NULL: the update equation of Sect. 1.1.  rhs != NULL: each sweep
+ * computes (six neighbours + rhs(i,j,k)) / 6, Jacobi's method for
+ * (6I - adjacency) e = rhs; rhs is a grid of the same dtype and geometry
+ * (shell ignored), read-only, not overlapping a or b.  With rhs the FP64
+ * result is not bitwise tied to a summation order (the rhs term is added
+ * before the last neighbour). */
+int jacobi_tblock(int dtype, const jac_grid_t *g, void *a, void *b, int T,
+                  const jac_tile_t *tile, const void *rhs, void *stream,
+                  int *out_idx);
+
+/* Adjoint of T sweeps.  The sweep map is linear: with x the interior and g the
+ * shell, x_s = M x_{s-1} + G g with M = (interior adjacency)/6, and the
+ * output's shell is g.  On entry lam_a holds dL/d(level T) for the whole
+ * array.  On return the buffer named by *out_idx holds dL/d(level 0):
+ *   interior:   lambda_0, where lambda_T = interior of the input and
+ *               lambda_{s-1} = M lambda_s;
+ *   face shell: input(b) + S_b / 6, S_b = lambda_T(in(b)) + ... + lambda_1(in(b))
+ *               summed in that order, in(b) the interior neighbour of b;
+ *   shell edges and corners: input(b).
+ * lam_b: second grid of the pair (contents ignored).  ws: device workspace
+ * of at least jacobi_adjoint_workspace(dtype, g, t) bytes (t as in tile,
+ * 0 = library choice), 256-byte aligned. */
+size_t jacobi_adjoint_workspace(int dtype, const jac_grid_t *g, int t);
+int jacobi_adjoint(int dtype, const jac_grid_t *g, void *lam_a, void *lam_b,
+                   int T, const jac_tile_t *tile, void *ws, size_t ws_bytes,
+                   void *stream, int *out_idx);
+
+/* Mixed-precision refinement helpers (outer FP64 loop of an FP32 Jacobi
+ * inner solve; not in the paper).
+ * jacobi_residual_f64: r = (six neighbours of x, left to right) - 6*x in
+ *   FP64 on the interior, i.e. b - A x for A = 6I - adjacency with the shell
+ *   of x as Dirichlet data; writes (float)r into r32's interior and zero into
+ *   r32's shell faces, and the squared 2-norm of the FP64 r into *norm2
+ *   (a device double), summed in a fixed order (deterministic run to run).
+ *   ws: at least jacobi_residual_workspace(g) bytes.
+ * jacobi_update_f64: x += (double)e32 on the interior. */
+size_t jacobi_residual_workspace(const jac_grid_t *g);
+int jacobi_residual_f64(const jac_grid_t *g, const double *x, float *r32,
+                        double *norm2, void *ws, size_t ws_bytes, void *stream);
+int jacobi_update_f64(const jac_grid_t *g, double *x, const float *e32,
+                      void *stream);
+
+/* Device copy dst[0..bytes) = src[0..bytes), the STREAM-COPY-like kernel that
+ * measures the bandwidth M_s of Eq. 2.  bytes must be a multiple of 16 and
+ * both pointers 16-byte aligned; the ranges must not overlap. */
+int jacobi_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Supported (bx, by) pairs for jacobi_tblock / jacobi_adjoint: writes up to
+ * `cap` pairs into pairs_host[2*n], [2*n+1] and returns the number available. */
+int jacobi_tile_menu(int dtype, int *pairs_host, int cap);
+
+/* The tile jacobi_tblock uses for (dtype, g, T, t) when tile fields are 0
+ * (t = 0: library choice of t as well).  Writes *tile_host; returns JAC_OK. */
+int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t,
+                        jac_tile_t *tile_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JACOBI_H */

@@ -1,0 +1,438 @@
+// Host side of libjacobi.so: the C ABI of include/jacobi.h.
+//
+// Every entry point validates its arguments before it makes any HIP call, so
+// the checks (and their error messages) are testable without a GPU.  Then it
+// plans the passes and enqueues kernels on the caller's stream.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "jacobi.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    return fail(JAC_EHIP, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+size_t elem_size(int dtype) { return dtype == JAC_F64 ? 8 : 4; }
+
+// Checked, normalised geometry.
+struct Geo {
+    int64_t nx, ny, nz, sy, sz;
+    int64_t span;  // elements from the first to one past the last element
+};
+
+int check_dtype(int dtype)
+{
+    if (dtype != JAC_F32 && dtype != JAC_F64)
+        return fail(JAC_EARG, "dtype must be JAC_F32 (0) or JAC_F64 (1), got %d", dtype);
+    return JAC_OK;
+}
+
+int check_grid(const jac_grid_t *g, Geo *out)
+{
+    if (!g)
+        return fail(JAC_EARG, "grid descriptor is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(JAC_EARG, "interior extents must be >= 1, got %lld x %lld x %lld",
+                    (long long)g->nx, (long long)g->ny, (long long)g->nz);
+    // kernels index planes and rows with 32-bit ints
+    if (g->nx > (1 << 28) || g->ny > (1 << 28) || g->nz > (1 << 28))
+        return fail(JAC_EARG, "interior extents above 2^28 are not supported");
+    Geo r;
+    r.nx = g->nx;
+    r.ny = g->ny;
+    r.nz = g->nz;
+    r.sy = g->sy ? g->sy : g->nx + 2;
+    r.sz = g->sz ? g->sz : r.sy * (g->ny + 2);
+    if (r.sy < r.nx + 2)
+        return fail(JAC_EARG, "sy = %lld is below nx+2 = %lld", (long long)r.sy, (long long)(r.nx + 2));
+    if (r.sz < r.sy * (r.ny + 2))
+        return fail(JAC_EARG, "sz = %lld is below sy*(ny+2) = %lld", (long long)r.sz,
+                    (long long)(r.sy * (r.ny + 2)));
+    const long double span = (long double)(r.nz + 1) * r.sz + (long double)(r.ny + 1) * r.sy + r.nx + 2;
+    if (span > (long double)(INT64_MAX / 16))
+        return fail(JAC_EARG, "grid too large");
+    r.span = (r.nz + 1) * r.sz + (r.ny + 1) * r.sy + r.nx + 2;
+    *out = r;
+    return JAC_OK;
+}
+
+int check_ptr(const void *p, int dtype, const char *name)
+{
+    if (!p)
+        return fail(JAC_EARG, "%s is NULL", name);
+    if ((uintptr_t)p % elem_size(dtype))
+        return fail(JAC_EARG, "%s is not aligned to its element size", name);
+    return JAC_OK;
+}
+
+bool overlap(const void *a, size_t abytes, const void *b, size_t bbytes)
+{
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+jac::GridArgs grid_args(const Geo &g)
+{
+    return jac::GridArgs{g.nx, g.ny, g.nz, g.sy, g.sz};
+}
+
+// ------------------------------------------------------------- device facts --
+struct DeviceFacts {
+    int cus = 256;
+    size_t lds_per_block = 160 * 1024;
+};
+
+DeviceFacts device_facts()
+{
+    // queried once per process for the current device; falls back to MI355X
+    // figures when no device is visible (argument checks still run)
+    static std::once_flag once;
+    static DeviceFacts f;
+    std::call_once(once, [] {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            if (prop.multiProcessorCount > 0)
+                f.cus = prop.multiProcessorCount;
+            if (prop.sharedMemPerBlock > 0)
+                f.lds_per_block = prop.sharedMemPerBlock;
+        }
+    });
+    return f;
+}
+
+// --------------------------------------------------------------- tile menu --
+const jac::TileShape kMenu[] = {
+#define JAC_ROW(ID, CI, R, W) jac::TileShape{ID, CI, R, W},
+    JAC_TILE_MENU(JAC_ROW)
+#undef JAC_ROW
+};
+const int kMenuN = (int)(sizeof kMenu / sizeof kMenu[0]);
+
+const jac::TileShape *find_shape(int bx, int by)
+{
+    for (int n = 0; n < kMenuN; ++n)
+        if (kMenu[n].bx() == bx && kMenu[n].by() == by)
+            return &kMenu[n];
+    return nullptr;
+}
+
+int even_up(int v) { return (v + 1) & ~1; }
+
+// Geometry of one temporally blocked pass at depth t with block shape s.
+struct TbPlan {
+    const jac::TileShape *shape;
+    int t;
+    int hi, vi, vj, nti, ntj, nkc, kchunk;
+    int64_t blocks() const { return (int64_t)nti * ntj * nkc; }
+};
+
+// Blocks along i and j for shape s at depth t; false if the block has no
+// valid cells at this depth.
+bool plan_ij(const Geo &g, const jac::TileShape &s, int t, TbPlan *p)
+{
+    p->shape = &s;
+    p->t = t;
+    p->hi = even_up(t);  // keeps the first i of a block even (16-byte aligned pairs)
+    p->vi = s.bx() - 2 * p->hi;
+    p->vj = s.by() - 2 * t;
+    if (p->vi < 1 || p->vj < 1)
+        return false;
+    p->nti = (int)((g.nx + p->vi) / p->vi);  // blocks cover i = 0 .. nti*vi-1 >= nx
+    p->ntj = (int)((g.ny + p->vj) / p->vj);
+    return true;
+}
+
+// Split k so that the blocks fill the chip: minimise the modelled time
+// ceil(blocks / slots) * (kchunk + 2t), the number of rounds times the
+// stream length of one block.
+void plan_k(const Geo &g, int slots, TbPlan *p, int kchunk_req)
+{
+    if (kchunk_req > 0) {
+        p->kchunk = (int)std::min<int64_t>(kchunk_req, g.nz);
+        p->nkc = (int)((g.nz + p->kchunk - 1) / p->kchunk);
+        return;
+    }
+    const int64_t nij = (int64_t)p->nti * p->ntj;
+    double best = 1e300;
+    int best_n = 1;
+    const int64_t nmax = std::min<int64_t>(g.nz, 4096);
+    for (int64_t n = 1; n <= nmax; ++n) {
+        const int64_t kc = (g.nz + n - 1) / n;
+        if ((g.nz + kc - 1) / kc != n)
+            continue;  // same chunking as a smaller n
+        const int64_t rounds = (nij * n + slots - 1) / slots;
+        const double cost = (double)rounds * (double)(kc + 2 * p->t);
+        if (cost < best * (1 - 1e-9)) {
+            best = cost;
+            best_n = (int)n;
+        }
+    }
+    p->kchunk = (int)((g.nz + best_n - 1) / best_n);
+    p->nkc = (int)((g.nz + p->kchunk - 1) / p->kchunk);
+}
+
+int default_depth(int dtype) { return dtype == JAC_F64 ? 4 : 6; }
+
+const jac::TileShape &default_shape(int dtype, int t)
+{
+    (void)dtype;
+    (void)t;
+    return kMenu[0];
+}
+
+// Largest LDS a depth-t block of shape s needs.
+size_t shape_lds(int dtype, const jac::TileShape &s, int t)
+{
+    return (size_t)s.waves * 2 * t * s.ci * 64 * elem_size(dtype);
+}
+
+int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out)
+{
+    jac_tile_t r = tile ? *tile : jac_tile_t{0, 0, 0, 0};
+    if (r.t < 0 || r.t > JAC_MAX_DEPTH)
+        return fail(JAC_EARG, "blocking depth t = %d outside 0..%d", r.t, JAC_MAX_DEPTH);
+    if (r.kchunk < 0)
+        return fail(JAC_EARG, "kchunk = %d is negative", r.kchunk);
+    if ((r.bx == 0) != (r.by == 0))
+        return fail(JAC_EARG, "bx and by must both be 0 (library choice) or both set");
+    if (r.bx && !find_shape(r.bx, r.by))
+        return fail(JAC_EUNSUPPORTED, "no kernel for block shape %d x %d (see jacobi_tile_menu)",
+                    r.bx, r.by);
+    if (r.t == 0)
+        r.t = default_depth(dtype);
+    if (T > 0 && r.t > T)
+        r.t = T;
+    if (r.bx == 0) {
+        const jac::TileShape &s = default_shape(dtype, r.t);
+        r.bx = s.bx();
+        r.by = s.by();
+    }
+    *out = r;
+    return JAC_OK;
+}
+
+// Enqueue the passes of a temporally blocked run; returns the pass count.
+template <typename real>
+int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, int mode,
+               const real *rhs, hipStream_t st, int *npasses)
+{
+    const jac::TileShape *shape = find_shape(tile.bx, tile.by);
+    const int dtype = sizeof(real) == 8 ? JAC_F64 : JAC_F32;
+    const int P = (T + tile.t - 1) / tile.t;
+    const DeviceFacts dev = device_facts();
+    hipError_t e = jac::launch_copy_shell<real>(a, b, grid_args(g), st);
+    if (e != hipSuccess)
+        return hip_fail(e, "shell copy");
+    for (int pass = 0; pass < P; ++pass) {
+        const int depth = T / P + (pass < T % P ? 1 : 0);
+        TbPlan plan;
+        if (!plan_ij(g, *shape, depth, &plan))
+            return fail(JAC_EUNSUPPORTED, "block %d x %d has no valid cells at depth %d", tile.bx,
+                        tile.by, depth);
+        if (shape_lds(dtype, *shape, depth) > dev.lds_per_block)
+            return fail(JAC_EUNSUPPORTED, "block %d x %d at depth %d needs more LDS than the device has",
+                        tile.bx, tile.by, depth);
+        int occ = jac::tblock_occupancy(dtype, shape->id, depth, mode);
+        if (occ < 1)
+            occ = 1;
+        plan_k(g, dev.cus * occ, &plan, tile.kchunk);
+        if (plan.blocks() > INT_MAX)
+            return fail(JAC_EUNSUPPORTED, "too many blocks");
+        jac::TbArgs<real> args;
+        args.src = (pass % 2 == 0) ? a : b;
+        args.dst = (pass % 2 == 0) ? b : a;
+        args.rhs = rhs;
+        args.trace = nullptr;
+        args.sy = g.sy;
+        args.sz = g.sz;
+        args.nx = (int)g.nx;
+        args.ny = (int)g.ny;
+        args.nz = (int)g.nz;
+        args.nti = plan.nti;
+        args.ntj = plan.ntj;
+        args.nkc = plan.nkc;
+        args.vi = plan.vi;
+        args.vj = plan.vj;
+        args.hi = plan.hi;
+        args.kchunk = plan.kchunk;
+        e = jac::launch_tblock<real>(shape->id, depth, mode, args, (int)plan.blocks(), st);
+        if (e != hipSuccess)
+            return hip_fail(e, "tblock launch");
+    }
+    *npasses = P;
+    return JAC_OK;
+}
+
+int check_pair(int dtype, const Geo &g, const void *a, const void *b)
+{
+    int rc;
+    if ((rc = check_ptr(a, dtype, "a")) || (rc = check_ptr(b, dtype, "b")))
+        return rc;
+    const size_t bytes = (size_t)g.span * elem_size(dtype);
+    if (overlap(a, bytes, b, bytes))
+        return fail(JAC_EARG, "grids a and b overlap");
+    return JAC_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI ==
+extern "C" {
+
+int jacobi_version(void) { return JACOBI_ABI_VERSION; }
+
+const char *jacobi_last_error(void) { return g_err.c_str(); }
+
+int jacobi_plain(int dtype, const jac_grid_t *g, void *a, void *b, int T, void *stream,
+                 int *out_idx)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_grid(g, &geo)) ||
+        (rc = check_pair(dtype, geo, a, b)))
+        return rc;
+    if (T < 0)
+        return fail(JAC_EARG, "T = %d is negative", T);
+    if (!out_idx)
+        return fail(JAC_EARG, "out_idx is NULL");
+    *out_idx = 0;
+    if (T == 0)
+        return JAC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int kchunk = 32;
+    jac::PlainArgs p{(int)geo.nx, (int)geo.ny, (int)geo.nz, kchunk, geo.sy, geo.sz};
+    hipError_t e;
+    if (dtype == JAC_F64)
+        e = jac::launch_copy_shell<double>((const double *)a, (double *)b, grid_args(geo), st);
+    else
+        e = jac::launch_copy_shell<float>((const float *)a, (float *)b, grid_args(geo), st);
+    if (e != hipSuccess)
+        return hip_fail(e, "shell copy");
+    for (int s = 0; s < T; ++s) {
+        void *src = (s % 2 == 0) ? a : b;
+        void *dst = (s % 2 == 0) ? b : a;
+        if (dtype == JAC_F64)
+            e = jac::launch_plain<double>((const double *)src, (double *)dst, p, st);
+        else
+            e = jac::launch_plain<float>((const float *)src, (float *)dst, p, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "plain sweep launch");
+    }
+    *out_idx = T % 2;
+    return JAC_OK;
+}
+
+int jacobi_tblock(int dtype, const jac_grid_t *g, void *a, void *b, int T, const jac_tile_t *tile,
+                  const void *rhs, void *stream, int *out_idx)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_grid(g, &geo)) ||
+        (rc = check_pair(dtype, geo, a, b)))
+        return rc;
+    if (T < 0)
+        return fail(JAC_EARG, "T = %d is negative", T);
+    if (!out_idx)
+        return fail(JAC_EARG, "out_idx is NULL");
+    if (rhs) {
+        if ((rc = check_ptr(rhs, dtype, "rhs")))
+            return rc;
+        const size_t bytes = (size_t)geo.span * elem_size(dtype);
+        if (overlap(rhs, bytes, a, bytes) || overlap(rhs, bytes, b, bytes))
+            return fail(JAC_EARG, "rhs overlaps a or b");
+    }
+    jac_tile_t tl;
+    if ((rc = resolve_tile(dtype, tile, T, &tl)))
+        return rc;
+    *out_idx = 0;
+    if (T == 0)
+        return JAC_OK;
+    const int mode = rhs ? jac::MODE_RHS : jac::MODE_PLAIN;
+    int P = 0;
+    if (dtype == JAC_F64)
+        rc = run_tblock<double>(geo, (double *)a, (double *)b, T, tl, mode, (const double *)rhs,
+                                (hipStream_t)stream, &P);
+    else
+        rc = run_tblock<float>(geo, (float *)a, (float *)b, T, tl, mode, (const float *)rhs,
+                               (hipStream_t)stream, &P);
+    if (rc)
+        return rc;
+    *out_idx = P % 2;
+    return JAC_OK;
+}
+
+int jacobi_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    g_err.clear();
+    if (!dst || !src)
+        return fail(JAC_EARG, "NULL pointer");
+    if ((uintptr_t)dst % 16 || (uintptr_t)src % 16 || bytes % 16)
+        return fail(JAC_EARG, "pointers and size must be multiples of 16 bytes");
+    if (overlap(dst, bytes, src, bytes))
+        return fail(JAC_EARG, "ranges overlap");
+    if (bytes == 0)
+        return JAC_OK;
+    hipError_t e = jac::launch_copy(dst, src, bytes, (hipStream_t)stream);
+    return e == hipSuccess ? JAC_OK : hip_fail(e, "copy launch");
+}
+
+int jacobi_tile_menu(int dtype, int *pairs_host, int cap)
+{
+    g_err.clear();
+    if (check_dtype(dtype))
+        return JAC_EARG;
+    if (cap < 0 || (cap > 0 && !pairs_host))
+        return fail(JAC_EARG, "bad output array");
+    for (int n = 0; n < kMenuN && n < cap; ++n) {
+        pairs_host[2 * n] = kMenu[n].bx();
+        pairs_host[2 * n + 1] = kMenu[n].by();
+    }
+    return kMenuN;
+}
+
+int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, jac_tile_t *tile_host)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_grid(g, &geo)))
+        return rc;
+    if (!tile_host)
+        return fail(JAC_EARG, "tile_host is NULL");
+    if (T < 0)
+        return fail(JAC_EARG, "T = %d is negative", T);
+    jac_tile_t req{t, 0, 0, 0};
+    if ((rc = resolve_tile(dtype, &req, T, tile_host)))
+        return rc;
+    return JAC_OK;
+}
+
+}  // extern "C"

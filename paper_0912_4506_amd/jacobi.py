@@ -1,0 +1,109 @@
+"""PyTorch-facing wrappers of libjacobi.so.
+
+Grids are torch tensors on the GPU of shape (nz+2, ny+2, nx+2), dtype float32
+or float64, with unit stride along the last axis (i); the other two strides
+may be padded.  PyTorch provides the device memory and the stream (the
+current stream of the tensor's device); every step runs in the library's
+kernels.  The wrappers only marshal arguments.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import Grid, Tile, check
+
+_DTYPES = {torch.float32: _lib.JAC_F32, torch.float64: _lib.JAC_F64}
+
+
+def dtype_code(x):
+    try:
+        return _DTYPES[x.dtype]
+    except KeyError:
+        raise TypeError(f"grids must be float32 or float64, got {x.dtype}") from None
+
+
+def grid_of(x):
+    """jac_grid_t of a (nz+2, ny+2, nx+2) tensor (strides in elements)."""
+    if x.dim() != 3:
+        raise ValueError(f"grid must be 3-D (nz+2, ny+2, nx+2), got shape {tuple(x.shape)}")
+    if x.stride(2) != 1:
+        raise ValueError("grid must be contiguous along i (last axis)")
+    nz, ny, nx = (s - 2 for s in x.shape)
+    return Grid(nx, ny, nz, x.stride(1), x.stride(0))
+
+
+def _same(a, b):
+    if a.shape != b.shape or a.dtype != b.dtype or a.device != b.device:
+        raise ValueError("grids must share shape, dtype and device")
+    if a.stride() != b.stride():
+        raise ValueError("grids must share strides")
+
+
+def _stream(x):
+    if not x.is_cuda:
+        raise ValueError("grids must live on the GPU")
+    return ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+
+def _tile(t=None, bx=0, by=0, kchunk=0):
+    return Tile(int(t or 0), int(bx or 0), int(by or 0), int(kchunk or 0))
+
+
+def plain(a, b, T):
+    """T plain sweeps; a holds level 0.  Returns the tensor (a or b) holding
+    level T."""
+    _same(a, b)
+    out = ctypes.c_int(0)
+    lib = _lib.load()
+    with torch.cuda.device(a.device):
+        check(lib.jacobi_plain(dtype_code(a), ctypes.byref(grid_of(a)), _ptr(a), _ptr(b), int(T),
+                               _stream(a), ctypes.byref(out)))
+    return b if out.value else a
+
+
+def tblock(a, b, T, t=None, bx=0, by=0, kchunk=0, rhs=None):
+    """T sweeps fused t per pass (t=None: library choice).  With rhs, each
+    sweep computes (six neighbours + rhs) / 6.  Returns the tensor holding
+    level T."""
+    _same(a, b)
+    if rhs is not None:
+        _same(a, rhs)
+    out = ctypes.c_int(0)
+    lib = _lib.load()
+    tile = _tile(t, bx, by, kchunk)
+    with torch.cuda.device(a.device):
+        check(lib.jacobi_tblock(dtype_code(a), ctypes.byref(grid_of(a)), _ptr(a), _ptr(b), int(T),
+                                ctypes.byref(tile), _ptr(rhs), _stream(a), ctypes.byref(out)))
+    return b if out.value else a
+
+
+def copy(dst, src):
+    """dst <- src with the library's copy kernel (the M_s probe)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("copy needs two contiguous tensors of the same byte size")
+    with torch.cuda.device(src.device):
+        check(_lib.load().jacobi_copy(_ptr(dst), _ptr(src), nbytes, _stream(src)))
+    return dst
+
+
+def tile_menu(dtype=torch.float64):
+    lib = _lib.load()
+    buf = (ctypes.c_int * 64)()
+    n = lib.jacobi_tile_menu(_DTYPES[dtype], buf, 32)
+    check(0 if n >= 0 else n)
+    return [(buf[2 * m], buf[2 * m + 1]) for m in range(n)]
+
+
+def default_tile(shape, T, t=0, dtype=torch.float64):
+    """Library choice of (t, bx, by, kchunk) for a (nz+2, ny+2, nx+2) grid."""
+    nz, ny, nx = (s - 2 for s in shape)
+    tile = Tile()
+    check(_lib.load().jacobi_default_tile(_DTYPES[dtype], ctypes.byref(Grid(nx, ny, nz, 0, 0)),
+                                          int(T), int(t), ctypes.byref(tile)))
+    return tile.t, tile.bx, tile.by, tile.kchunk

@@ -18,3 +18,25 @@ def oracle_mod():
     import oracle
     oracle._load()
     return oracle
+
+
+@pytest.hookimpl(trylast=True)
+def pytest_collection_modifyitems(config, items):
+    gpu_items = [it for it in items if "gpu" in it.keywords]
+    if not gpu_items:
+        return
+    import torch
+    if torch.cuda.is_available():
+        return
+    skip = pytest.mark.skip(reason="no GPU visible")
+    for it in gpu_items:
+        it.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def jac():
+    """The GPU binding; fails loudly when libjacobi.so is missing."""
+    from paper_0912_4506_amd import jacobi
+    from paper_0912_4506_amd import _lib
+    _lib.load()
+    return jacobi
