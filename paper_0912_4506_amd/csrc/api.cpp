@@ -148,23 +148,34 @@ int even_up(int v) { return (v + 1) & ~1; }
 struct TbPlan {
     const jac::TileShape *shape;
     int t;
-    int hi, vi, vj, nti, ntj, nkc, kchunk;
+    int hi, nti, ntj, nkc, kchunk;
     int64_t blocks() const { return (int64_t)nti * ntj * nkc; }
 };
 
-// Blocks along i and j for shape s at depth t; false if the block has no
+// Blocks along one axis of n interior cells for blocks w wide with halo h:
+// block 0 is valid on [1, w-h), every further block on w-2h more cells.
+int64_t axis_blocks(int64_t n, int w, int h)
+{
+    const int64_t first = w - h, mid = w - 2 * h;
+    if (first >= n + 1)
+        return 1;
+    return 1 + (n + 1 - first + mid - 1) / mid;
+}
+
+// Blocks along i and j for shape s at depth t; false if a block has no
 // valid cells at this depth.
 bool plan_ij(const Geo &g, const jac::TileShape &s, int t, TbPlan *p)
 {
     p->shape = &s;
     p->t = t;
-    p->hi = even_up(t);  // keeps the first i of a block even (16-byte aligned pairs)
-    p->vi = s.bx() - 2 * p->hi;
-    p->vj = s.by() - 2 * t;
-    if (p->vi < 1 || p->vj < 1)
+    p->hi = (s.ci % 2 == 0) ? even_up(t) : t;  // even first i keeps CI-wide pairs aligned
+    if (s.bx() - 2 * p->hi < 1 || s.by() - 2 * t < 1)
         return false;
-    p->nti = (int)((g.nx + p->vi) / p->vi);  // blocks cover i = 0 .. nti*vi-1 >= nx
-    p->ntj = (int)((g.ny + p->vj) / p->vj);
+    const int64_t ni = axis_blocks(g.nx, s.bx(), p->hi), nj = axis_blocks(g.ny, s.by(), t);
+    if (ni > INT_MAX / 2 || nj > INT_MAX / 2)
+        return false;
+    p->nti = (int)ni;
+    p->ntj = (int)nj;
     return true;
 }
 
@@ -209,7 +220,8 @@ const jac::TileShape &default_shape(int dtype, int t)
 // Largest LDS a depth-t block of shape s needs.
 size_t shape_lds(int dtype, const jac::TileShape &s, int t)
 {
-    return (size_t)s.waves * 2 * t * s.ci * 64 * elem_size(dtype);
+    const size_t one = (size_t)s.waves * 2 * t * s.ci * 64 * elem_size(dtype);
+    return 2 * one <= 160 * 1024 ? 2 * one : one;  // double-buffered when it fits
 }
 
 int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out)
@@ -277,8 +289,6 @@ int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, in
         args.nti = plan.nti;
         args.ntj = plan.ntj;
         args.nkc = plan.nkc;
-        args.vi = plan.vi;
-        args.vj = plan.vj;
         args.hi = plan.hi;
         args.kchunk = plan.kchunk;
         e = jac::launch_tblock<real>(shape->id, depth, mode, args, (int)plan.blocks(), st);

@@ -12,7 +12,11 @@
 //   W waves are stacked in j, so a workgroup covers (64*CI) x (W*R) cells.
 #define JAC_TILE_MENU(X) \
     X(0, 2, 4, 8)        \
-    X(1, 1, 8, 8)
+    X(1, 1, 8, 8)        \
+    X(2, 1, 6, 8)        \
+    X(3, 2, 3, 8)        \
+    X(4, 1, 4, 8)        \
+    X(5, 2, 2, 8)
 
 namespace jac {
 
@@ -36,8 +40,7 @@ struct TbArgs {
     int64_t sy, sz;
     int nx, ny, nz;
     int nti, ntj, nkc;  // blocks along i, j, k
-    int vi, vj;         // valid (written) extent of a block in i and j
-    int hi;             // i-halo: the block's first i is ti*vi - hi
+    int hi;             // i-halo (>= depth; even when CI is even, for alignment)
     int kchunk;         // output planes per block along k
 };
 

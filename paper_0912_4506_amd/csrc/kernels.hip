@@ -38,20 +38,21 @@ __device__ __forceinline__ float div6(float s)
 
 // ------------------------------------------------------- cross-lane moves --
 // DPP wave shifts (GFX9 wave_shr:1 / wave_shl:1): lane l receives the value
-// of lane l-1 (shr) or l+1 (shl).  The lane with no source keeps 0.
+// of lane l-1 (shr) or l+1 (shl); bound_ctrl makes the lane with no source
+// read 0, so no old value has to be materialised.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v)
 {
     const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
-    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+    const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, true);
+    const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, true);
     return __hiloint2double(h2, l2);
 }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 
 constexpr int DPP_WAVE_SHL1 = 0x130;
@@ -99,95 +100,138 @@ __global__ __launch_bounds__(256) void plain_kernel(const real *__restrict__ A,
 }
 
 // -------------------------------------------------- temporally blocked pass --
+// Block placement along one axis.  Blocks are w cells wide including a halo
+// of h cells per side.  Block 0 starts at the shell cell 0, which passes its
+// value through unchanged at every level, so it needs no halo on that side:
+// its valid range is [1, w - h).  Block b >= 1 is valid on [a, a + w - 2h)
+// and starts at e = a - h.  Valid ranges tile [1, n] without overlap.
+struct AxisTile {
+    int e, a, b;  // first cell of the block; valid cells [a, b)
+};
+
+__device__ __forceinline__ AxisTile axis_tile(int blk, int n, int w, int h)
+{
+    const int first = w - h, mid = w - 2 * h;
+    AxisTile t;
+    if (blk == 0) {
+        t.e = 0;
+        t.a = 1;
+        t.b = first;
+    } else {
+        t.a = first + (blk - 1) * mid;
+        t.e = t.a - h;
+        t.b = t.a + mid;
+    }
+    t.b = min(t.b, n + 1);
+    return t;
+}
+
+// Workgroup ids reach the eight XCDs round robin (id mod 8), and each XCD has
+// its own L2.  Remap so that XCD x works through a contiguous range of
+// logical blocks: blocks that share halo cells then run on the same L2 at the
+// same time.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int q = n >> 3, rem = n & 7, x = b & 7, idx = b >> 3;
+    return x * q + min(x, rem) + idx;
+}
+
+// The exchange buffer is double-buffered (one barrier per stream step) when
+// two copies fit in the 160 KiB of LDS a gfx950 workgroup may use.
+template <typename real, int TL, int CI, int W>
+constexpr bool xch_double()
+{
+    return 2 * (W * 2 * TL * CI * 64) * sizeof(real) <= 160 * 1024;
+}
+
+template <typename real, int TL, int CI, int W>
+constexpr size_t xch_bytes()
+{
+    return (xch_double<real, TL, CI, W>() ? 2 : 1) * (size_t)(W * 2 * TL * CI * 64) * sizeof(real);
+}
+
 // One pass fuses TL sweeps.  A workgroup of W waves owns an extended block of
 // (64*CI) x (W*R) cells in (i, j): lane l of wave w holds cells
-// i = i0 + CI*l + c (c < CI) and j = j0 + w*R + r (r < R) in registers.  The
+// i = e_i + CI*l + c (c < CI) and j = e_j + w*R + r (r < R) in registers.  The
 // block streams through k.  At stream step k, level 0 (the input) supplies
 // plane k and level s (1..TL) completes plane k - s, so the levels form a
 // wavefront skewed by one plane per level.  Halo cells are recomputed: the
-// valid part of level s shrinks by one cell per side and level (the rule
-// that update s covers a region h - s layers larger, Sect. 2.1), so the
-// block writes only its central (64*CI - 2h) x (W*R - 2TL) cells.
+// valid part of level s shrinks by one cell per side and level (the rule that
+// update s covers a region h - s layers larger, Sect. 2.1), and the block
+// writes only its valid cells.
 //
 // Per level s and cell the kernel keeps two values:
-//   Q = level s-1 at the plane being completed (centre; it is the k-1 term of
-//       the next plane and the pass-through value of shell cells), and
+//   Q = level s-1 at the plane being completed (it is the k-1 term of the next
+//       plane, and the value a shell cell passes through), and
 //   P = ((((W + E) + S) + N) + D) of that plane, the first five terms of the
-//       update in the printed order (D = k-1 neighbour).
+//       update in the printed order (D = the k-1 neighbour).
 // When level s-1 delivers the next plane U, level s completes its plane as
 // (P + U) / 6 -- the full left-to-right sum -- with no neighbour exchange, so
 // the levels run back to back.  Then the newly delivered planes of all levels
 // are exchanged at once (i-neighbours by DPP wave shifts, j-neighbours from
-// registers, and across wave boundaries through LDS) and P, Q advance.
-// Shell cells (i, j or k = 0 or n+1) pass their value through at every level.
+// registers, and across wave boundaries through LDS) and P, Q advance.  The
+// stream loop is unrolled twice with the two Q sets swapping roles, so no
+// register copies carry Q from one step to the next.
+// Loads clamp their coordinates into the array: cells outside it hold
+// garbage that only ever reaches other outside cells or shell cells, and
+// shell cells (i, j or k = 0 or n+1) pass their value through at every level.
 template <typename real, int TL, int CI, int R, int W, int MODE>
 __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
 {
     static_assert(TL >= 1 && TL <= JAC_MAX_DEPTH_DEV, "depth");
     extern __shared__ unsigned char smem_raw[];
-    real *xch = reinterpret_cast<real *>(smem_raw);  // [W][2][TL][CI][64]
+    real *xch = reinterpret_cast<real *>(smem_raw);  // [2][W][2][TL][CI][64]
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    // block -> (ti, tj, tk); ti fastest
-    const int bid = blockIdx.x;
+    const int bid = xcd_remap(blockIdx.x, p.nti * p.ntj * p.nkc);
     const int ti = bid % p.nti;
     const int tj = (bid / p.nti) % p.ntj;
     const int tk = bid / (p.nti * p.ntj);
-
-    const int i0 = ti * p.vi - p.hi;       // first i of the extended block
-    const int j0 = tj * p.vj - TL;         // first j
-    const int vi0 = max(ti * p.vi, 1), vi1 = min((ti + 1) * p.vi, p.nx + 1);
-    const int vj0 = max(tj * p.vj, 1), vj1 = min((tj + 1) * p.vj, p.ny + 1);
+    const AxisTile xi = axis_tile(ti, p.nx, 64 * CI, p.hi);
+    const AxisTile xj = axis_tile(tj, p.ny, W * R, TL);
     const int k0 = 1 + tk * p.kchunk;
     const int k1 = min(k0 + p.kchunk, p.nz + 1);
     const int kstart = max(k0 - TL, 0);
-    const int kend = k1 - 1 + TL;
+    const int nsteps = ((k1 - 1 + TL) - kstart + 2) & ~1;  // rounded up to even
 
     // per-lane columns
-    int ii[CI];
-    bool in_i[CI], sh_i[CI], ok_i[CI];
+    int ic[CI];
+    bool sh_i[CI], ok_i[CI];
 #pragma unroll
     for (int c = 0; c < CI; ++c) {
-        ii[c] = i0 + CI * lane + c;
-        in_i[c] = ii[c] >= 0 && ii[c] <= p.nx + 1;
-        sh_i[c] = ii[c] == 0 || ii[c] == p.nx + 1;
-        ok_i[c] = ii[c] >= vi0 && ii[c] < vi1;
+        const int i = xi.e + CI * lane + c;
+        ic[c] = min(max(i, 0), p.nx + 1);
+        sh_i[c] = i == 0 || i == p.nx + 1;
+        ok_i[c] = i >= xi.a && i < xi.b;
     }
-    const bool fix_i = (i0 <= 0) || (i0 + 64 * CI - 1 >= p.nx + 1);  // uniform
+    const bool fix_i = xi.e <= 0 || xi.e + 64 * CI - 1 >= p.nx + 1;
     // per-wave rows (uniform)
-    int jj[R];
-    bool in_j[R], sh_j[R], ok_j[R];
+    int64_t rowoff[R];
+    bool sh_j[R], ok_j[R];
     bool fix_j = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        jj[r] = j0 + w * R + r;
-        in_j[r] = jj[r] >= 0 && jj[r] <= p.ny + 1;
-        sh_j[r] = jj[r] == 0 || jj[r] == p.ny + 1;
-        ok_j[r] = jj[r] >= vj0 && jj[r] < vj1;
+        const int j = xj.e + w * R + r;
+        rowoff[r] = (int64_t)min(max(j, 0), p.ny + 1) * p.sy;
+        sh_j[r] = j == 0 || j == p.ny + 1;
+        ok_j[r] = j >= xj.a && j < xj.b;
         fix_j = fix_j || sh_j[r];
     }
 
-    // offsets of this lane's cells within a plane (int64: grids exceed 4 GiB)
-    int64_t off[R][CI];
+    auto load_plane = [&](const real *__restrict__ src, int k, real(&v)[R][CI]) {
+        const real *plane = src + (int64_t)min(max(k, 0), p.nz + 1) * p.sz;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int c = 0; c < CI; ++c)
-            off[r][c] = (int64_t)ii[c] + (int64_t)jj[r] * p.sy;
-
-    auto load_plane = [&](const real *__restrict__ src, int k, real (&v)[R][CI]) {
-        const bool kin = k >= 0 && k <= p.nz + 1;
-        const int64_t ko = (int64_t)k * p.sz;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int r = 0; r < R; ++r) {
+            const real *row = plane + rowoff[r];
 #pragma unroll
             for (int c = 0; c < CI; ++c)
-                v[r][c] = (kin && in_j[r] && in_i[c]) ? src[ko + off[r][c]] : real(0);
+                v[r][c] = row[ic[c]];
+        }
     };
 
-    real P[TL][R][CI], Q[TL][R][CI];
+    real P[TL][R][CI], QA[TL][R][CI], QB[TL][R][CI];
 #pragma unroll
     for (int s = 0; s < TL; ++s)
 #pragma unroll
@@ -195,31 +239,56 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
 #pragma unroll
             for (int c = 0; c < CI; ++c) {
                 P[s][r][c] = real(0);
-                Q[s][r][c] = real(0);
+                QA[s][r][c] = real(0);
+                QB[s][r][c] = real(0);
             }
-    // right-hand side window: rw[s] holds rhs at plane k-1-s (MODE_RHS only)
-    real rw[MODE == MODE_RHS ? TL : 1][R][CI];
+    constexpr int NRW = MODE == MODE_RHS ? TL : 1;
+    real rw[NRW][R][CI];  // rw[s] = rhs at plane k-1-s (MODE_RHS)
+    real rnext[R][CI];
 #pragma unroll
-    for (int s = 0; s < (MODE == MODE_RHS ? TL : 1); ++s)
+    for (int s = 0; s < NRW; ++s)
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < CI; ++c)
                 rw[s][r][c] = real(0);
-    real rnext[R][CI];
     if constexpr (MODE == MODE_RHS)
         load_plane(p.rhs, kstart - 1, rnext);
 
-    real cur[R][CI];
-    load_plane(p.src, kstart, cur);
+    real CA[R][CI], CB[R][CI];
+    load_plane(p.src, kstart, CA);
 
-    for (int k = kstart; k <= kend; ++k) {
-        real nxt[R][CI];
-        load_plane(p.src, k + 1 <= kend ? k + 1 : -1, nxt);
-        if constexpr (MODE == MODE_RHS) {
-            // shift the window: rw[s] = rhs(k-1-s)
+    const int wa = w > 0 ? w - 1 : w;      // wave holding row j-1 of row 0
+    const int wb = w < W - 1 ? w + 1 : w;  // wave holding row j+1 of row R-1
+    // exchange buffer: one or two parities of [W][2 rows][TL][CI][64 lanes]
+    constexpr int XSLAB = W * 2 * TL * CI * 64;
+    constexpr bool DBUF = xch_double<real, TL, CI, W>();
+    auto xidx = [](int wv, int side, int s, int c, int ln) {
+        return (((wv * 2 + side) * TL + s) * CI + c) * 64 + ln;
+    };
+    for (int n = threadIdx.x; n < (DBUF ? 2 : 1) * XSLAB; n += 64 * W)
+        xch[n] = real(0);
+    __syncthreads();
+    // i-neighbours of a row of CI cells: DPP across lanes at the ends
+    auto neighbours_i = [](const real(&x)[CI], real(&west)[CI], real(&east)[CI]) {
+        west[0] = from_left(x[CI - 1]);
+        east[CI - 1] = from_right(x[0]);
 #pragma unroll
-            for (int s = TL - 1; s > 0; --s)
+        for (int c = 1; c < CI; ++c)
+            west[c] = x[c - 1];
+#pragma unroll
+        for (int c = 0; c < CI - 1; ++c)
+            east[c] = x[c + 1];
+    };
+
+    // One stream step: Qi = Q carried in, Qo = Q carried out (the planes
+    // delivered this step), cur = plane k of level 0, nxt = prefetch of k+1.
+    auto step = [&](int k, real(&Qi)[TL][R][CI], real(&Qo)[TL][R][CI], real(&cur)[R][CI],
+                    real(&nxt)[R][CI]) {
+        load_plane(p.src, k + 1, nxt);
+        if constexpr (MODE == MODE_RHS) {
+#pragma unroll
+            for (int s = NRW - 1; s > 0; --s)
 #pragma unroll
                 for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -232,16 +301,19 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
                     rw[0][r][c] = rnext[r][c];
             load_plane(p.rhs, k, rnext);
         }
-
-        // V[s] = plane delivered to level s+1 this step (level s at plane k-s)
-        real V[TL][R][CI];
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < CI; ++c)
-                V[0][r][c] = cur[r][c];
+                Qo[0][r][c] = cur[r][c];
 
-        // ---- complete one plane per level, back to back
+        // ---- complete one plane per level, back to back; right after level s
+        // completes, advance P[s-1] for the rows whose j-neighbours are in
+        // registers.  The wave's first and last rows are finished after the
+        // exchange; their Q values live in LDS (own slot, previous parity).
+        const int par = DBUF ? (k & 1) : 0;
+        real *xcur = xch + par * XSLAB;
+        const real *xold = xch + (DBUF ? (par ^ 1) : 0) * XSLAB;
 #pragma unroll
         for (int s = 1; s <= TL; ++s) {
             const int plane = k - s;
@@ -250,27 +322,35 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
             for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int c = 0; c < CI; ++c) {
-                    real sum = P[s - 1][r][c] + V[s - 1][r][c];
+                    real sum = P[s - 1][r][c] + Qo[s - 1][r][c];
                     if constexpr (MODE == MODE_RHS)
                         sum = sum + rw[s - 1][r][c];
                     o[r][c] = div6(sum);
                 }
-            const bool sh_plane = plane == 0 || plane == p.nz + 1;
+            // pass-through value of a shell cell: its level s-1 value
+            auto qin = [&](int r, int c) -> real {
+                if (r == 0)
+                    return xold[xidx(w, 0, s - 1, c, lane)];
+                if (r == R - 1)
+                    return xold[xidx(w, 1, s - 1, c, lane)];
+                return Qi[s - 1][r][c];
+            };
             if (fix_i) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
 #pragma unroll
                     for (int c = 0; c < CI; ++c)
                         if (sh_i[c])
-                            o[r][c] = Q[s - 1][r][c];
+                            o[r][c] = qin(r, c);
             }
+            const bool sh_plane = plane == 0 || plane == p.nz + 1;
             if (sh_plane || fix_j) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (sh_plane || sh_j[r]) {
 #pragma unroll
                         for (int c = 0; c < CI; ++c)
-                            o[r][c] = Q[s - 1][r][c];
+                            o[r][c] = qin(r, c);
                     }
             }
             if (s < TL) {
@@ -278,74 +358,93 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
                 for (int r = 0; r < R; ++r)
 #pragma unroll
                     for (int c = 0; c < CI; ++c)
-                        V[s][r][c] = o[r][c];
+                        Qo[s][r][c] = o[r][c];
             } else if (plane >= k0 && plane < k1) {
-                const int64_t ko = (int64_t)plane * p.sz;
+                real *dplane = p.dst + (int64_t)plane * p.sz;
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (ok_j[r]) {
+                        real *row = dplane + rowoff[r];
 #pragma unroll
                         for (int c = 0; c < CI; ++c)
                             if (ok_i[c])
-                                p.dst[ko + off[r][c]] = o[r][c];
+                                row[ic[c]] = o[r][c];
                     }
+            }
+            // advance P[s-1] (rows 1 .. R-2) from the plane delivered to level s
+            const int l = s - 1;
+#pragma unroll
+            for (int r = 1; r < R - 1; ++r) {
+                real west[CI], east[CI];
+                neighbours_i(Qo[l][r], west, east);
+#pragma unroll
+                for (int c = 0; c < CI; ++c) {
+                    real q = west[c] + east[c];
+                    q = q + Qo[l][r - 1][c];
+                    q = q + Qo[l][r + 1][c];
+                    P[l][r][c] = q + Qi[l][r][c];
+                }
             }
         }
 
-        // ---- exchange the delivered planes and advance P, Q
-        __syncthreads();  // previous step's readers are done with xch
+        // ---- publish the wave's first and last rows, then finish their P.
+        // With one buffer, the old rows are read back before they are
+        // overwritten, and a barrier keeps the previous step's readers safe.
+        real dold[TL][2][CI];
+        if constexpr (!DBUF) {
+#pragma unroll
+            for (int s = 0; s < TL; ++s)
+#pragma unroll
+                for (int c = 0; c < CI; ++c) {
+                    dold[s][0][c] = xold[xidx(w, 0, s, c, lane)];
+                    dold[s][1][c] = xold[xidx(w, 1, s, c, lane)];
+                }
+            __syncthreads();
+        }
 #pragma unroll
         for (int s = 0; s < TL; ++s)
 #pragma unroll
             for (int c = 0; c < CI; ++c) {
-                xch[(((w * 2 + 0) * TL + s) * CI + c) * 64 + lane] = V[s][0][c];
-                xch[(((w * 2 + 1) * TL + s) * CI + c) * 64 + lane] = V[s][R - 1][c];
+                xcur[xidx(w, 0, s, c, lane)] = Qo[s][0][c];
+                xcur[xidx(w, 1, s, c, lane)] = Qo[s][R - 1][c];
             }
         __syncthreads();
-        const int wa = w > 0 ? w - 1 : w;      // wave holding row j-1 of row 0
-        const int wb = w < W - 1 ? w + 1 : w;  // wave holding row j+1 of row R-1
+        auto dprev = [&](int side, int s, int c) -> real {
+            if constexpr (DBUF)
+                return xold[xidx(w, side, s, c, lane)];
+            else
+                return dold[s][side][c];
+        };
 #pragma unroll
         for (int s = 0; s < TL; ++s) {
-            real sn[CI], nn[CI];
+            real west[CI], east[CI];
+            neighbours_i(Qo[s][0], west, east);
 #pragma unroll
             for (int c = 0; c < CI; ++c) {
-                sn[c] = xch[(((wa * 2 + 1) * TL + s) * CI + c) * 64 + lane];
-                nn[c] = xch[(((wb * 2 + 0) * TL + s) * CI + c) * 64 + lane];
+                const real sn = xcur[xidx(wa, 1, s, c, lane)];
+                const real north = R > 1 ? Qo[s][R > 1 ? 1 : 0][c] : xcur[xidx(wb, 0, s, c, lane)];
+                real q = west[c] + east[c];
+                q = q + sn;
+                q = q + north;
+                P[s][0][c] = q + dprev(0, s, c);
             }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                real west[CI], east[CI];
-                west[0] = from_left(V[s][r][CI - 1]);
-                east[CI - 1] = from_right(V[s][r][0]);
-#pragma unroll
-                for (int c = 1; c < CI; ++c)
-                    west[c] = V[s][r][c - 1];
-#pragma unroll
-                for (int c = 0; c < CI - 1; ++c)
-                    east[c] = V[s][r][c + 1];
+            if constexpr (R > 1) {
+                neighbours_i(Qo[s][R - 1], west, east);
 #pragma unroll
                 for (int c = 0; c < CI; ++c) {
-                    const real south = r > 0 ? V[s][r - 1][c] : sn[c];
-                    const real north = r < R - 1 ? V[s][r + 1][c] : nn[c];
+                    const real nn = xcur[xidx(wb, 0, s, c, lane)];
                     real q = west[c] + east[c];
-                    q = q + south;
-                    q = q + north;
-                    q = q + Q[s][r][c];
-                    P[s][r][c] = q;
+                    q = q + Qo[s][R - 2][c];
+                    q = q + nn;
+                    P[s][R - 1][c] = q + dprev(1, s, c);
                 }
             }
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int c = 0; c < CI; ++c)
-                    Q[s][r][c] = V[s][r][c];
         }
+    };
 
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < CI; ++c)
-                cur[r][c] = nxt[r][c];
+    for (int n = 0; n < nsteps; n += 2) {
+        step(kstart + n, QA, QB, CA, CB);
+        step(kstart + n + 1, QB, QA, CB, CA);
     }
 }
 
@@ -408,7 +507,7 @@ template <typename real, int TL, int CI, int R, int W, int MODE>
 static KernInfo tb_info_one()
 {
     return KernInfo{(const void *)tblock_kernel<real, TL, CI, R, W, MODE>,
-                    (size_t)W * 2 * TL * CI * 64 * sizeof(real), 64 * W};
+                    xch_bytes<real, TL, CI, W>(), 64 * W};
 }
 
 template <typename real, int CI, int R, int W, int MODE>

@@ -22,6 +22,13 @@ def dev(u, dtype=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(u)).to("cuda", dtype)
 
 
+def fits(bx, by, t):
+    """A block has valid cells at depth t (halo t per side; i-halo even for
+    blocks two cells per lane wide)."""
+    hi = t + (t % 2) if bx % 128 == 0 else t
+    return bx - 2 * hi >= 1 and by - 2 * t >= 1
+
+
 def run(jac, u, T, method="tblock", dtype=torch.float64, **kw):
     a = dev(u, dtype)
     b = torch.full_like(a, float("nan"))   # b's prior contents must not matter
@@ -43,6 +50,8 @@ def test_config0_tblock_fp64_bitwise_all_depths(jac, t):
     u = inputs.grid(64, 64, 64, seed=0)
     ref = oracle.sweeps(u, 10)
     for bx, by in jac.tile_menu(torch.float64):
+        if not fits(bx, by, t):
+            continue
         got = run(jac, u, 10, t=t, bx=bx, by=by)
         assert np.array_equal(got, ref), (t, bx, by)
 
@@ -73,9 +82,22 @@ def test_ragged_shapes_bitwise(jac, shape, T, t, kchunk):
     u = inputs.grid(nx, ny, nz, seed=hash(shape) % 1000)
     ref = oracle.sweeps(u, T)
     for bx, by in jac.tile_menu(torch.float64):
+        if not fits(bx, by, t):
+            continue
         got = run(jac, u, T, t=t, bx=bx, by=by, kchunk=kchunk)
         assert np.array_equal(got, ref), (shape, T, t, bx, by, kchunk)
     assert np.array_equal(run(jac, u, T, "plain"), ref)
+
+
+def test_unsupported_depth_is_an_error(jac):
+    """A block too small for the depth is refused (no kernel runs)."""
+    from paper_0912_4506_amd._lib import JacobiError, JAC_EUNSUPPORTED
+    u = inputs.grid(20, 20, 20, seed=1)
+    for bx, by in jac.tile_menu(torch.float64):
+        if not fits(bx, by, 8):
+            with pytest.raises(JacobiError) as e:
+                run(jac, u, 8, t=8, bx=bx, by=by)
+            assert e.value.code == JAC_EUNSUPPORTED
 
 
 def test_padded_strides(jac):
