@@ -249,10 +249,24 @@ int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out)
     return JAC_OK;
 }
 
-// Enqueue the passes of a temporally blocked run; returns the pass count.
+// Per-level size of the compact shell-face arrays: 2(ny nz + nx nz + nx ny).
+int64_t face_count(const Geo &g) { return 2 * (g.ny * g.nz + g.nx * g.nz + g.nx * g.ny); }
+
+// Extra work of the adjoint around the passes: each pass records the values
+// of its levels next to the shell (trace) and folds them into the running
+// face sums S, in level order.
+template <typename real>
+struct TraceSink {
+    real *trace = nullptr;
+    real *S = nullptr;
+    int64_t F = 0;
+};
+
+// Enqueue the passes of a temporally blocked run (after copying a's shell
+// into b); *npasses receives the pass count.
 template <typename real>
 int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, int mode,
-               const real *rhs, hipStream_t st, int *npasses)
+               const real *rhs, const TraceSink<real> &sink, hipStream_t st, int *npasses)
 {
     const jac::TileShape *shape = find_shape(tile.bx, tile.by);
     const int dtype = sizeof(real) == 8 ? JAC_F64 : JAC_F32;
@@ -280,7 +294,7 @@ int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, in
         args.src = (pass % 2 == 0) ? a : b;
         args.dst = (pass % 2 == 0) ? b : a;
         args.rhs = rhs;
-        args.trace = nullptr;
+        args.trace = sink.trace;
         args.sy = g.sy;
         args.sz = g.sz;
         args.nx = (int)g.nx;
@@ -290,12 +304,49 @@ int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, in
         args.ntj = plan.ntj;
         args.nkc = plan.nkc;
         args.hi = plan.hi;
+        args.fstride = sink.F;
         args.kchunk = plan.kchunk;
         e = jac::launch_tblock<real>(shape->id, depth, mode, args, (int)plan.blocks(), st);
         if (e != hipSuccess)
             return hip_fail(e, "tblock launch");
+        if (mode == jac::MODE_TRACE) {
+            e = jac::launch_faces<real>(jac::FACES_ACCUM, nullptr, nullptr, sink.S, sink.trace,
+                                        grid_args(g), sink.F, depth, st);
+            if (e != hipSuccess)
+                return hip_fail(e, "face accumulation");
+        }
     }
     *npasses = P;
+    return JAC_OK;
+}
+
+size_t adjoint_ws_bytes(int dtype, const Geo &g, int t)
+{
+    return (size_t)(2 + t) * (size_t)face_count(g) * elem_size(dtype);
+}
+
+template <typename real>
+int run_adjoint(const Geo &g, real *la, real *lb, int T, const jac_tile_t &tile, void *ws,
+                hipStream_t st, int *npasses)
+{
+    const int64_t F = face_count(g);
+    real *G = (real *)ws, *S = G + F, *TR = S + F;
+    const jac::GridArgs ga = grid_args(g);
+    hipError_t e;
+    if ((e = jac::launch_faces<real>(jac::FACES_SAVE, la, G, nullptr, nullptr, ga, F, 0, st)) ||
+        (e = jac::launch_faces<real>(jac::FACES_ZERO, la, nullptr, nullptr, nullptr, ga, F, 0, st)) ||
+        (e = jac::launch_faces<real>(jac::FACES_CLEAR_SUM, nullptr, nullptr, S, nullptr, ga, F, 0, st)))
+        return hip_fail(e, "adjoint set-up");
+    TraceSink<real> sink;
+    sink.trace = TR;
+    sink.S = S;
+    sink.F = F;
+    int rc = run_tblock<real>(g, la, lb, T, tile, jac::MODE_TRACE, nullptr, sink, st, npasses);
+    if (rc)
+        return rc;
+    real *res = (*npasses % 2) ? lb : la;
+    if ((e = jac::launch_faces<real>(jac::FACES_FINALIZE, res, G, S, nullptr, ga, F, 0, st)))
+        return hip_fail(e, "adjoint shell gradient");
     return JAC_OK;
 }
 
@@ -336,7 +387,11 @@ int jacobi_plain(int dtype, const jac_grid_t *g, void *a, void *b, int T, void *
     if (T == 0)
         return JAC_OK;
     hipStream_t st = (hipStream_t)stream;
-    const int kchunk = 32;
+    // k-chunk: long streams (contiguous reads), but enough blocks to fill the chip
+    const int64_t strips = ((geo.nx + 511) / 512) * ((geo.ny + 7) / 8);
+    int64_t nkc = ((int64_t)device_facts().cus + strips - 1) / strips;
+    nkc = std::max<int64_t>(1, std::min<int64_t>(nkc, geo.nz));
+    const int kchunk = (int)((geo.nz + nkc - 1) / nkc);
     jac::PlainArgs p{(int)geo.nx, (int)geo.ny, (int)geo.nz, kchunk, geo.sy, geo.sz};
     hipError_t e;
     if (dtype == JAC_F64)
@@ -389,10 +444,67 @@ int jacobi_tblock(int dtype, const jac_grid_t *g, void *a, void *b, int T, const
     int P = 0;
     if (dtype == JAC_F64)
         rc = run_tblock<double>(geo, (double *)a, (double *)b, T, tl, mode, (const double *)rhs,
-                                (hipStream_t)stream, &P);
+                                TraceSink<double>(), (hipStream_t)stream, &P);
     else
         rc = run_tblock<float>(geo, (float *)a, (float *)b, T, tl, mode, (const float *)rhs,
-                               (hipStream_t)stream, &P);
+                               TraceSink<float>(), (hipStream_t)stream, &P);
+    if (rc)
+        return rc;
+    *out_idx = P % 2;
+    return JAC_OK;
+}
+
+size_t jacobi_adjoint_workspace(int dtype, const jac_grid_t *g, int t)
+{
+    g_err.clear();
+    Geo geo;
+    if (check_dtype(dtype) || check_grid(g, &geo))
+        return 0;
+    if (t < 0 || t > JAC_MAX_DEPTH) {
+        fail(JAC_EARG, "blocking depth t = %d outside 0..%d", t, JAC_MAX_DEPTH);
+        return 0;
+    }
+    if (t == 0)
+        t = JAC_MAX_DEPTH;  // room for any depth the library may choose
+    return adjoint_ws_bytes(dtype, geo, t);
+}
+
+int jacobi_adjoint(int dtype, const jac_grid_t *g, void *lam_a, void *lam_b, int T,
+                   const jac_tile_t *tile, void *ws, size_t ws_bytes, void *stream, int *out_idx)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_grid(g, &geo)) ||
+        (rc = check_pair(dtype, geo, lam_a, lam_b)))
+        return rc;
+    if (T < 0)
+        return fail(JAC_EARG, "T = %d is negative", T);
+    if (!out_idx)
+        return fail(JAC_EARG, "out_idx is NULL");
+    jac_tile_t tl;
+    if ((rc = resolve_tile(dtype, tile, T, &tl)))
+        return rc;
+    *out_idx = 0;
+    if (T == 0)
+        return JAC_OK;  // the gradient w.r.t. level 0 is the input itself
+    const size_t need = adjoint_ws_bytes(dtype, geo, tl.t);
+    if (!ws)
+        return fail(JAC_EWORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+    if (ws_bytes < need)
+        return fail(JAC_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    if ((uintptr_t)ws % elem_size(dtype))
+        return fail(JAC_EARG, "workspace is not aligned to the element size");
+    const size_t gbytes = (size_t)geo.span * elem_size(dtype);
+    if (overlap(ws, need, lam_a, gbytes) || overlap(ws, need, lam_b, gbytes))
+        return fail(JAC_EARG, "workspace overlaps lam_a or lam_b");
+    int P = 0;
+    if (dtype == JAC_F64)
+        rc = run_adjoint<double>(geo, (double *)lam_a, (double *)lam_b, T, tl, ws,
+                                 (hipStream_t)stream, &P);
+    else
+        rc = run_adjoint<float>(geo, (float *)lam_a, (float *)lam_b, T, tl, ws,
+                                (hipStream_t)stream, &P);
     if (rc)
         return rc;
     *out_idx = P % 2;

@@ -18,7 +18,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "api.cpp"]
+SOURCES = ["tb_plain_f64.hip", "tb_plain_f32.hip", "tb_rhs_f64.hip", "tb_rhs_f32.hip",
+           "tb_trace_f64.hip", "tb_trace_f32.hip", "kernels.hip", "api.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -51,7 +52,8 @@ def _compile(src, verbose):
 def build(verbose=False, jobs=None):
     """Compile every source and link libjacobi.so; returns its path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=jobs or len(SOURCES)) as ex:
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

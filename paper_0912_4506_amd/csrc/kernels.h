@@ -21,6 +21,7 @@
 namespace jac {
 
 enum { MODE_PLAIN = 0, MODE_RHS = 1, MODE_TRACE = 2 };
+enum { FACES_SAVE = 0, FACES_ZERO = 1, FACES_CLEAR_SUM = 2, FACES_ACCUM = 3, FACES_FINALIZE = 4 };
 
 struct GridArgs {
     int64_t nx, ny, nz, sy, sz;
@@ -41,8 +42,24 @@ struct TbArgs {
     int nx, ny, nz;
     int nti, ntj, nkc;  // blocks along i, j, k
     int hi;             // i-halo (>= depth; even when CI is even, for alignment)
+    int64_t fstride;    // MODE_TRACE: values per level of the face trace
     int kchunk;         // output planes per block along k
 };
+
+// A compiled kernel instance: entry point, dynamic LDS bytes, threads per block.
+struct KernInfo {
+    const void *fn;
+    size_t lds;
+    int threads;
+};
+
+// Instances of the temporally blocked pass per mode and dtype (tb_*.hip).
+KernInfo tb_info_plain_f64(int cfg, int depth);
+KernInfo tb_info_plain_f32(int cfg, int depth);
+KernInfo tb_info_rhs_f64(int cfg, int depth);
+KernInfo tb_info_rhs_f32(int cfg, int depth);
+KernInfo tb_info_trace_f64(int cfg, int depth);
+KernInfo tb_info_trace_f32(int cfg, int depth);
 
 struct TileShape {
     int id, ci, rows, waves;
@@ -58,6 +75,12 @@ hipError_t launch_tblock(int cfg, int depth, int mode, const TbArgs<real> &p, in
 template <typename real>
 hipError_t launch_copy_shell(const real *a, real *b, const GridArgs &g, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+// Shell-face helpers of the adjoint (FACES_*): save grid faces into G, zero
+// the grid's faces, clear S, accumulate S += trace levels in order, or write
+// grid faces = G + S/6.
+template <typename real>
+hipError_t launch_faces(int op, real *grid, real *G, real *S, const real *tr, const GridArgs &g,
+                        int64_t F, int depth, hipStream_t st);
 
 // Resident workgroups per CU of a tblock instance (0 when it cannot launch).
 int tblock_occupancy(int dtype, int cfg, int depth, int mode);

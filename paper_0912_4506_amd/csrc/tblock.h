@@ -1,0 +1,460 @@
+// The temporally blocked pass (a template instantiated per dtype and mode in
+// tb_*.hip).  Arithmetic contract: the six neighbours are summed left to
+// right in the printed order (i-1, i+1, j-1, j+1, k-1, k+1); FP64 divides by 6
+// with a correctly rounded quotient, FP32 multiplies by the float nearest 1/6.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace jac {
+
+// -------------------------------------------------- temporally blocked pass --
+// Block placement along one axis.  Blocks are w cells wide including a halo
+// of h cells per side.  Block 0 starts at the shell cell 0, which passes its
+// value through unchanged at every level, so it needs no halo on that side:
+// its valid range is [1, w - h).  Block b >= 1 is valid on [a, a + w - 2h)
+// and starts at e = a - h.  Valid ranges tile [1, n] without overlap.
+struct AxisTile {
+    int e, a, b;  // first cell of the block; valid cells [a, b)
+};
+
+__device__ __forceinline__ AxisTile axis_tile(int blk, int n, int w, int h)
+{
+    const int first = w - h, mid = w - 2 * h;
+    AxisTile t;
+    if (blk == 0) {
+        t.e = 0;
+        t.a = 1;
+        t.b = first;
+    } else {
+        t.a = first + (blk - 1) * mid;
+        t.e = t.a - h;
+        t.b = t.a + mid;
+    }
+    t.b = min(t.b, n + 1);
+    return t;
+}
+
+// Workgroup ids reach the eight XCDs round robin (id mod 8), and each XCD has
+// its own L2.  Remap so that XCD x works through a contiguous range of
+// logical blocks: blocks that share halo cells then run on the same L2 at the
+// same time.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int q = n >> 3, rem = n & 7, x = b & 7, idx = b >> 3;
+    return x * q + min(x, rem) + idx;
+}
+
+// The exchange buffer is double-buffered (one barrier per stream step) when
+// two copies fit in the 160 KiB of LDS a gfx950 workgroup may use.
+template <typename real, int TL, int CI, int W>
+constexpr bool xch_double()
+{
+    return 2 * (W * 2 * TL * CI * 64) * sizeof(real) <= 160 * 1024;
+}
+
+template <typename real, int TL, int CI, int W>
+constexpr size_t xch_bytes()
+{
+    return (xch_double<real, TL, CI, W>() ? 2 : 1) * (size_t)(W * 2 * TL * CI * 64) * sizeof(real);
+}
+
+// One pass fuses TL sweeps.  A workgroup of W waves owns an extended block of
+// (64*CI) x (W*R) cells in (i, j): lane l of wave w holds cells
+// i = e_i + CI*l + c (c < CI) and j = e_j + w*R + r (r < R) in registers.  The
+// block streams through k.  At stream step k, level 0 (the input) supplies
+// plane k and level s (1..TL) completes plane k - s, so the levels form a
+// wavefront skewed by one plane per level.  Halo cells are recomputed: the
+// valid part of level s shrinks by one cell per side and level (the rule that
+// update s covers a region h - s layers larger, Sect. 2.1), and the block
+// writes only its valid cells.
+//
+// Per level s and cell the kernel keeps two values:
+//   Q = level s-1 at the plane being completed (it is the k-1 term of the next
+//       plane, and the value a shell cell passes through), and
+//   P = ((((W + E) + S) + N) + D) of that plane, the first five terms of the
+//       update in the printed order (D = the k-1 neighbour).
+// When level s-1 delivers the next plane U, level s completes its plane as
+// (P + U) / 6 -- the full left-to-right sum -- with no neighbour exchange, so
+// the levels run back to back.  Then the newly delivered planes of all levels
+// are exchanged at once (i-neighbours by DPP wave shifts, j-neighbours from
+// registers, and across wave boundaries through LDS) and P, Q advance.  The
+// stream loop is unrolled twice with the two Q sets swapping roles, so no
+// register copies carry Q from one step to the next.
+// Loads clamp their coordinates into the array: cells outside it hold
+// garbage that only ever reaches other outside cells or shell cells, and
+// shell cells (i, j or k = 0 or n+1) pass their value through at every level.
+template <typename real, int TL, int CI, int R, int W, int MODE>
+__global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
+{
+    static_assert(TL >= 1 && TL <= JAC_MAX_DEPTH_DEV, "depth");
+    extern __shared__ unsigned char smem_raw[];
+    real *xch = reinterpret_cast<real *>(smem_raw);  // [2][W][2][TL][CI][64]
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    const int bid = xcd_remap(blockIdx.x, p.nti * p.ntj * p.nkc);
+    const int ti = bid % p.nti;
+    const int tj = (bid / p.nti) % p.ntj;
+    const int tk = bid / (p.nti * p.ntj);
+    const AxisTile xi = axis_tile(ti, p.nx, 64 * CI, p.hi);
+    const AxisTile xj = axis_tile(tj, p.ny, W * R, TL);
+    const int k0 = 1 + tk * p.kchunk;
+    const int k1 = min(k0 + p.kchunk, p.nz + 1);
+    const int kstart = max(k0 - TL, 0);
+    const int nsteps = ((k1 - 1 + TL) - kstart + 2) & ~1;  // rounded up to even
+
+    // per-lane columns
+    int ic[CI];
+    bool sh_i[CI], ok_i[CI];
+#pragma unroll
+    for (int c = 0; c < CI; ++c) {
+        const int i = xi.e + CI * lane + c;
+        ic[c] = min(max(i, 0), p.nx + 1);
+        sh_i[c] = i == 0 || i == p.nx + 1;
+        ok_i[c] = i >= xi.a && i < xi.b;
+    }
+    const bool fix_i = xi.e <= 0 || xi.e + 64 * CI - 1 >= p.nx + 1;
+    // per-wave rows (uniform)
+    int64_t rowoff[R];
+    int jrow[R];
+    bool sh_j[R], ok_j[R];
+    bool fix_j = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = xj.e + w * R + r;
+        jrow[r] = j;
+        rowoff[r] = (int64_t)min(max(j, 0), p.ny + 1) * p.sy;
+        sh_j[r] = j == 0 || j == p.ny + 1;
+        ok_j[r] = j >= xj.a && j < xj.b;
+        fix_j = fix_j || sh_j[r];
+    }
+
+    auto load_plane = [&](const real *__restrict__ src, int k, real(&v)[R][CI]) {
+        const real *plane = src + (int64_t)min(max(k, 0), p.nz + 1) * p.sz;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const real *row = plane + rowoff[r];
+#pragma unroll
+            for (int c = 0; c < CI; ++c)
+                v[r][c] = row[ic[c]];
+        }
+    };
+
+    // MODE_TRACE: record level s at the interior cells next to the shell (the
+    // cells whose values the adjoint adds into the shell gradient).  Face
+    // arrays of one level, F = 2(ny nz + nx nz + nx ny) values: i = 1 face
+    // [k][j], i = nx face, j = 1 face [k][i], j = ny face, k = 1 face [j][i],
+    // k = nz face.  Each value is written by the one block whose output
+    // region holds the cell.
+    auto trace_level = [&](int s, int plane, const real(&v)[R][CI]) {
+        if constexpr (MODE == MODE_TRACE) {
+            if (plane < k0 || plane >= k1)
+                return;
+            real *tr = p.trace + (int64_t)s * p.fstride;
+            const int64_t nyz = (int64_t)p.ny * p.nz, nxz = (int64_t)p.nx * p.nz;
+            const int64_t nxy = (int64_t)p.nx * p.ny;
+            real *fi = tr, *fj = tr + 2 * nyz, *fk = tr + 2 * nyz + 2 * nxz;
+            const bool klo = plane == 1, khi = plane == p.nz;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!ok_j[r])
+                    continue;
+                const int j = jrow[r];
+                const bool jlo = j == 1, jhi = j == p.ny;
+                if (klo || khi || jlo || jhi) {
+#pragma unroll
+                    for (int c = 0; c < CI; ++c) {
+                        if (!ok_i[c])
+                            continue;
+                        const int i = ic[c];
+                        if (klo)
+                            fk[(int64_t)(j - 1) * p.nx + (i - 1)] = v[r][c];
+                        if (khi)
+                            fk[nxy + (int64_t)(j - 1) * p.nx + (i - 1)] = v[r][c];
+                        if (jlo)
+                            fj[(int64_t)(plane - 1) * p.nx + (i - 1)] = v[r][c];
+                        if (jhi)
+                            fj[nxz + (int64_t)(plane - 1) * p.nx + (i - 1)] = v[r][c];
+                    }
+                }
+                if (fix_i) {
+#pragma unroll
+                    for (int c = 0; c < CI; ++c) {
+                        if (!ok_i[c])
+                            continue;
+                        const int i = ic[c];
+                        if (i == 1)
+                            fi[(int64_t)(plane - 1) * p.ny + (j - 1)] = v[r][c];
+                        if (i == p.nx)
+                            fi[nyz + (int64_t)(plane - 1) * p.ny + (j - 1)] = v[r][c];
+                    }
+                }
+            }
+        } else {
+            (void)s;
+            (void)plane;
+            (void)v;
+        }
+    };
+
+    real P[TL][R][CI], QA[TL][R][CI], QB[TL][R][CI];
+#pragma unroll
+    for (int s = 0; s < TL; ++s)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < CI; ++c) {
+                P[s][r][c] = real(0);
+                QA[s][r][c] = real(0);
+                QB[s][r][c] = real(0);
+            }
+    constexpr int NRW = MODE == MODE_RHS ? TL : 1;
+    real rw[NRW][R][CI];  // rw[s] = rhs at plane k-1-s (MODE_RHS)
+    real rnext[R][CI];
+#pragma unroll
+    for (int s = 0; s < NRW; ++s)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < CI; ++c)
+                rw[s][r][c] = real(0);
+    if constexpr (MODE == MODE_RHS)
+        load_plane(p.rhs, kstart - 1, rnext);
+
+    real CA[R][CI], CB[R][CI];
+    load_plane(p.src, kstart, CA);
+
+    const int wa = w > 0 ? w - 1 : w;      // wave holding row j-1 of row 0
+    const int wb = w < W - 1 ? w + 1 : w;  // wave holding row j+1 of row R-1
+    // exchange buffer: one or two parities of [W][2 rows][TL][CI][64 lanes]
+    constexpr int XSLAB = W * 2 * TL * CI * 64;
+    constexpr bool DBUF = xch_double<real, TL, CI, W>();
+    auto xidx = [](int wv, int side, int s, int c, int ln) {
+        return (((wv * 2 + side) * TL + s) * CI + c) * 64 + ln;
+    };
+    for (int n = threadIdx.x; n < (DBUF ? 2 : 1) * XSLAB; n += 64 * W)
+        xch[n] = real(0);
+    __syncthreads();
+    // i-neighbours of a row of CI cells: DPP across lanes at the ends
+    auto neighbours_i = [](const real(&x)[CI], real(&west)[CI], real(&east)[CI]) {
+        west[0] = from_left(x[CI - 1]);
+        east[CI - 1] = from_right(x[0]);
+#pragma unroll
+        for (int c = 1; c < CI; ++c)
+            west[c] = x[c - 1];
+#pragma unroll
+        for (int c = 0; c < CI - 1; ++c)
+            east[c] = x[c + 1];
+    };
+
+    // One stream step: Qi = Q carried in, Qo = Q carried out (the planes
+    // delivered this step), cur = plane k of level 0, nxt = prefetch of k+1.
+    auto step = [&](int k, real(&Qi)[TL][R][CI], real(&Qo)[TL][R][CI], real(&cur)[R][CI],
+                    real(&nxt)[R][CI]) {
+        load_plane(p.src, k + 1, nxt);
+        if constexpr (MODE == MODE_RHS) {
+#pragma unroll
+            for (int s = NRW - 1; s > 0; --s)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < CI; ++c)
+                        rw[s][r][c] = rw[s - 1][r][c];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < CI; ++c)
+                    rw[0][r][c] = rnext[r][c];
+            load_plane(p.rhs, k, rnext);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < CI; ++c)
+                Qo[0][r][c] = cur[r][c];
+        trace_level(0, k, Qo[0]);
+
+        // ---- complete one plane per level, back to back; right after level s
+        // completes, advance P[s-1] for the rows whose j-neighbours are in
+        // registers.  The wave's first and last rows are finished after the
+        // exchange; their Q values live in LDS (own slot, previous parity).
+        const int par = DBUF ? (k & 1) : 0;
+        real *xcur = xch + par * XSLAB;
+        const real *xold = xch + (DBUF ? (par ^ 1) : 0) * XSLAB;
+#pragma unroll
+        for (int s = 1; s <= TL; ++s) {
+            const int plane = k - s;
+            real o[R][CI];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < CI; ++c) {
+                    real sum = P[s - 1][r][c] + Qo[s - 1][r][c];
+                    if constexpr (MODE == MODE_RHS)
+                        sum = sum + rw[s - 1][r][c];
+                    o[r][c] = div6(sum);
+                }
+            // pass-through value of a shell cell: its level s-1 value
+            auto qin = [&](int r, int c) -> real {
+                if (r == 0)
+                    return xold[xidx(w, 0, s - 1, c, lane)];
+                if (r == R - 1)
+                    return xold[xidx(w, 1, s - 1, c, lane)];
+                return Qi[s - 1][r][c];
+            };
+            if (fix_i) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < CI; ++c)
+                        if (sh_i[c])
+                            o[r][c] = qin(r, c);
+            }
+            const bool sh_plane = plane == 0 || plane == p.nz + 1;
+            if (sh_plane || fix_j) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (sh_plane || sh_j[r]) {
+#pragma unroll
+                        for (int c = 0; c < CI; ++c)
+                            o[r][c] = qin(r, c);
+                    }
+            }
+            if (s < TL) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < CI; ++c)
+                        Qo[s][r][c] = o[r][c];
+                trace_level(s, plane, Qo[s]);
+            } else if (plane >= k0 && plane < k1) {
+                real *dplane = p.dst + (int64_t)plane * p.sz;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (ok_j[r]) {
+                        real *row = dplane + rowoff[r];
+#pragma unroll
+                        for (int c = 0; c < CI; ++c)
+                            if (ok_i[c])
+                                row[ic[c]] = o[r][c];
+                    }
+            }
+            // advance P[s-1] (rows 1 .. R-2) from the plane delivered to level s
+            const int l = s - 1;
+#pragma unroll
+            for (int r = 1; r < R - 1; ++r) {
+                real west[CI], east[CI];
+                neighbours_i(Qo[l][r], west, east);
+#pragma unroll
+                for (int c = 0; c < CI; ++c) {
+                    real q = west[c] + east[c];
+                    q = q + Qo[l][r - 1][c];
+                    q = q + Qo[l][r + 1][c];
+                    P[l][r][c] = q + Qi[l][r][c];
+                }
+            }
+        }
+
+        // ---- publish the wave's first and last rows, then finish their P.
+        // With one buffer, the old rows are read back before they are
+        // overwritten, and a barrier keeps the previous step's readers safe.
+        real dold[TL][2][CI];
+        if constexpr (!DBUF) {
+#pragma unroll
+            for (int s = 0; s < TL; ++s)
+#pragma unroll
+                for (int c = 0; c < CI; ++c) {
+                    dold[s][0][c] = xold[xidx(w, 0, s, c, lane)];
+                    dold[s][1][c] = xold[xidx(w, 1, s, c, lane)];
+                }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int s = 0; s < TL; ++s)
+#pragma unroll
+            for (int c = 0; c < CI; ++c) {
+                xcur[xidx(w, 0, s, c, lane)] = Qo[s][0][c];
+                xcur[xidx(w, 1, s, c, lane)] = Qo[s][R - 1][c];
+            }
+        __syncthreads();
+        auto dprev = [&](int side, int s, int c) -> real {
+            if constexpr (DBUF)
+                return xold[xidx(w, side, s, c, lane)];
+            else
+                return dold[s][side][c];
+        };
+#pragma unroll
+        for (int s = 0; s < TL; ++s) {
+            real west[CI], east[CI];
+            neighbours_i(Qo[s][0], west, east);
+#pragma unroll
+            for (int c = 0; c < CI; ++c) {
+                const real sn = xcur[xidx(wa, 1, s, c, lane)];
+                const real north = R > 1 ? Qo[s][R > 1 ? 1 : 0][c] : xcur[xidx(wb, 0, s, c, lane)];
+                real q = west[c] + east[c];
+                q = q + sn;
+                q = q + north;
+                P[s][0][c] = q + dprev(0, s, c);
+            }
+            if constexpr (R > 1) {
+                neighbours_i(Qo[s][R - 1], west, east);
+#pragma unroll
+                for (int c = 0; c < CI; ++c) {
+                    const real nn = xcur[xidx(wb, 0, s, c, lane)];
+                    real q = west[c] + east[c];
+                    q = q + Qo[s][R - 2][c];
+                    q = q + nn;
+                    P[s][R - 1][c] = q + dprev(1, s, c);
+                }
+            }
+        }
+    };
+
+    for (int n = 0; n < nsteps; n += 2) {
+        step(kstart + n, QA, QB, CA, CB);
+        step(kstart + n + 1, QB, QA, CB, CA);
+    }
+}
+
+template <typename real, int TL, int CI, int R, int W, int MODE>
+static KernInfo tb_info_one()
+{
+    return KernInfo{(const void *)tblock_kernel<real, TL, CI, R, W, MODE>,
+                    xch_bytes<real, TL, CI, W>(), 64 * W};
+}
+
+template <typename real, int CI, int R, int W, int MODE>
+static KernInfo tb_info_depth(int depth)
+{
+    switch (depth) {
+    case 1: return tb_info_one<real, 1, CI, R, W, MODE>();
+    case 2: return tb_info_one<real, 2, CI, R, W, MODE>();
+    case 3: return tb_info_one<real, 3, CI, R, W, MODE>();
+    case 4: return tb_info_one<real, 4, CI, R, W, MODE>();
+    case 5: return tb_info_one<real, 5, CI, R, W, MODE>();
+    case 6: return tb_info_one<real, 6, CI, R, W, MODE>();
+    case 7: return tb_info_one<real, 7, CI, R, W, MODE>();
+    case 8: return tb_info_one<real, 8, CI, R, W, MODE>();
+    default: return KernInfo{nullptr, 0, 0};
+    }
+}
+
+template <typename real, int MODE>
+static KernInfo tb_info_mode(int cfg, int depth)
+{
+#define JAC_CFG(ID, CI, R, W) \
+    case ID: return tb_info_depth<real, CI, R, W, MODE>(depth);
+    switch (cfg) {
+        JAC_TILE_MENU(JAC_CFG)
+    default: return KernInfo{nullptr, 0, 0};
+    }
+#undef JAC_CFG
+}
+
+}  // namespace jac

@@ -107,3 +107,26 @@ def default_tile(shape, T, t=0, dtype=torch.float64):
     check(_lib.load().jacobi_default_tile(_DTYPES[dtype], ctypes.byref(Grid(nx, ny, nz, 0, 0)),
                                           int(T), int(t), ctypes.byref(tile)))
     return tile.t, tile.bx, tile.by, tile.kchunk
+
+
+def adjoint_workspace(like, t=0):
+    """Device workspace (uint8 tensor) for adjoint() on grids shaped like ``like``."""
+    n = _lib.load().jacobi_adjoint_workspace(dtype_code(like), ctypes.byref(grid_of(like)), int(t or 0))
+    if n == 0:
+        check(_lib.JAC_EARG)
+    return torch.empty(n, dtype=torch.uint8, device=like.device)
+
+
+def adjoint(lam_a, lam_b, T, t=None, bx=0, by=0, kchunk=0, ws=None):
+    """Adjoint of T sweeps.  lam_a holds dL/d(level T) (whole grid); returns the
+    tensor (lam_a or lam_b) holding dL/d(level 0): interior and shell."""
+    _same(lam_a, lam_b)
+    if ws is None:
+        ws = adjoint_workspace(lam_a, t or 0)
+    out = ctypes.c_int(0)
+    tile = _tile(t, bx, by, kchunk)
+    with torch.cuda.device(lam_a.device):
+        check(_lib.load().jacobi_adjoint(dtype_code(lam_a), ctypes.byref(grid_of(lam_a)),
+                                         _ptr(lam_a), _ptr(lam_b), int(T), ctypes.byref(tile),
+                                         _ptr(ws), ws.numel(), _stream(lam_a), ctypes.byref(out)))
+    return lam_b if out.value else lam_a
