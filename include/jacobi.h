@@ -107,9 +107,9 @@ int jacobi_plain(int dtype, const jac_grid_t *g, void *a, void *b, int T,
  * rhs == NULL: the update equation of Sect. 1.1.  rhs != NULL: each sweep
  * computes (six neighbours + rhs(i,j,k)) / 6, Jacobi's method for
  * (6I - adjacency) e = rhs; rhs is a grid of the same dtype and geometry
- * (shell ignored), read-only, not overlapping a or b.  With rhs the FP64
- * result is not bitwise tied to a summation order (the rhs term is added
- * before the last neighbour). */
+ * (shell ignored), read-only, not overlapping a or b.  The rhs term is added
+ * after the six neighbours, so FP64 results stay bitwise those of the plain
+ * sequential iteration. */
 int jacobi_tblock(int dtype, const jac_grid_t *g, void *a, void *b, int T,
                   const jac_tile_t *tile, const void *rhs, void *stream,
                   int *out_idx);
@@ -125,26 +125,33 @@ int jacobi_tblock(int dtype, const jac_grid_t *g, void *a, void *b, int T,
  *   shell edges and corners: input(b).
  * lam_b: second grid of the pair (contents ignored).  ws: device workspace
  * of at least jacobi_adjoint_workspace(dtype, g, t) bytes (t as in tile,
- * 0 = library choice), 256-byte aligned. */
+ * 0 = library choice), aligned to the element size, not overlapping the grids.
+ * T = 0 enqueues nothing: the input is the gradient (*out_idx = 0). */
 size_t jacobi_adjoint_workspace(int dtype, const jac_grid_t *g, int t);
 int jacobi_adjoint(int dtype, const jac_grid_t *g, void *lam_a, void *lam_b,
                    int T, const jac_tile_t *tile, void *ws, size_t ws_bytes,
                    void *stream, int *out_idx);
 
-/* Mixed-precision refinement helpers (outer FP64 loop of an FP32 Jacobi
- * inner solve; not in the paper).
+/* Mixed-precision refinement helpers (outer FP64 loop around an FP32 Jacobi
+ * inner solve; the refinement is not in the paper, the operator is the
+ * Laplace system whose fixed point the Jacobi iteration of Sect. 1.1 seeks).
  * jacobi_residual_f64: r = (six neighbours of x, left to right) - 6*x in
  *   FP64 on the interior, i.e. b - A x for A = 6I - adjacency with the shell
- *   of x as Dirichlet data; writes (float)r into r32's interior and zero into
- *   r32's shell faces, and the squared 2-norm of the FP64 r into *norm2
- *   (a device double), summed in a fixed order (deterministic run to run).
- *   ws: at least jacobi_residual_workspace(g) bytes.
- * jacobi_update_f64: x += (double)e32 on the interior. */
+ *   of x as Dirichlet data.  Writes (float)r into r32's interior (r32's shell
+ *   is not written) and the squared 2-norm of the FP64 r into *norm2 (a
+ *   device double), summed in a fixed order, so the result is identical run
+ *   to run.  x and r32 share the geometry g (r32 holds floats).  ws: device
+ *   workspace of at least jacobi_residual_workspace(g) bytes, 8-byte aligned.
+ * jacobi_update_f64: x += (double)e32 on the interior.
+ * jacobi_fill: every element of a grid, shell included, set to `value`
+ *   (converted to the grid's dtype). */
 size_t jacobi_residual_workspace(const jac_grid_t *g);
 int jacobi_residual_f64(const jac_grid_t *g, const double *x, float *r32,
                         double *norm2, void *ws, size_t ws_bytes, void *stream);
 int jacobi_update_f64(const jac_grid_t *g, double *x, const float *e32,
                       void *stream);
+int jacobi_fill(int dtype, const jac_grid_t *g, void *x, double value,
+                void *stream);
 
 /* Device copy dst[0..bytes) = src[0..bytes), the STREAM-COPY-like kernel that
  * measures the bandwidth M_s of Eq. 2.  bytes must be a multiple of 16 and

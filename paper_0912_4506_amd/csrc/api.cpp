@@ -511,6 +511,69 @@ int jacobi_adjoint(int dtype, const jac_grid_t *g, void *lam_a, void *lam_b, int
     return JAC_OK;
 }
 
+size_t jacobi_residual_workspace(const jac_grid_t *g)
+{
+    g_err.clear();
+    Geo geo;
+    if (check_grid(g, &geo))
+        return 0;
+    return (size_t)jac::residual_partials(grid_args(geo)) * sizeof(double);
+}
+
+int jacobi_residual_f64(const jac_grid_t *g, const double *x, float *r32, double *norm2, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_grid(g, &geo)) || (rc = check_ptr(x, JAC_F64, "x")) ||
+        (rc = check_ptr(r32, JAC_F32, "r32")) || (rc = check_ptr(norm2, JAC_F64, "norm2")))
+        return rc;
+    const size_t need = (size_t)jac::residual_partials(grid_args(geo)) * sizeof(double);
+    if (!ws)
+        return fail(JAC_EWORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+    if (ws_bytes < need)
+        return fail(JAC_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    if ((uintptr_t)ws % 8)
+        return fail(JAC_EARG, "workspace is not 8-byte aligned");
+    const size_t xb = (size_t)geo.span * 8, rb = (size_t)geo.span * 4;
+    if (overlap(x, xb, r32, rb) || overlap(ws, need, x, xb) || overlap(ws, need, r32, rb) ||
+        overlap(norm2, 8, x, xb) || overlap(norm2, 8, r32, rb) || overlap(norm2, 8, ws, need))
+        return fail(JAC_EARG, "x, r32, norm2 and the workspace must not overlap");
+    hipError_t e = jac::launch_residual(x, r32, (double *)ws, norm2, grid_args(geo),
+                                        (hipStream_t)stream);
+    return e == hipSuccess ? JAC_OK : hip_fail(e, "residual launch");
+}
+
+int jacobi_update_f64(const jac_grid_t *g, double *x, const float *e32, void *stream)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_grid(g, &geo)) || (rc = check_ptr(x, JAC_F64, "x")) ||
+        (rc = check_ptr(e32, JAC_F32, "e32")))
+        return rc;
+    if (overlap(x, (size_t)geo.span * 8, e32, (size_t)geo.span * 4))
+        return fail(JAC_EARG, "x and e32 overlap");
+    hipError_t e = jac::launch_update(x, e32, grid_args(geo), (hipStream_t)stream);
+    return e == hipSuccess ? JAC_OK : hip_fail(e, "update launch");
+}
+
+int jacobi_fill(int dtype, const jac_grid_t *g, void *x, double value, void *stream)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_grid(g, &geo)) || (rc = check_ptr(x, dtype, "x")))
+        return rc;
+    hipError_t e = dtype == JAC_F64
+                       ? jac::launch_grid_fill<double>((double *)x, value, grid_args(geo),
+                                                       (hipStream_t)stream)
+                       : jac::launch_grid_fill<float>((float *)x, (float)value, grid_args(geo),
+                                                      (hipStream_t)stream);
+    return e == hipSuccess ? JAC_OK : hip_fail(e, "fill launch");
+}
+
 int jacobi_copy(void *dst, const void *src, size_t bytes, void *stream)
 {
     g_err.clear();

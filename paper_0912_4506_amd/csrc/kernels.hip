@@ -134,6 +134,102 @@ __global__ void copy_shell_kernel(const real *__restrict__ a, real *__restrict__
     }
 }
 
+// ------------------------------------------------- refinement (FP64 outer) --
+// Residual of the Laplace system whose fixed point the Jacobi iteration seeks:
+// r = (six neighbours of x, summed left to right) - 6x on the interior, FP64,
+// i.e. b - A x for A = 6I - adjacency with the shell of x as Dirichlet data.
+// Writes (float)r to r32 (interior) and a per-block partial sum of r^2.  Blocks own row strips
+// of RES_ROWS rows x 256 cells and a k chunk; each thread sums its cells in
+// order, the block sums its threads with a fixed tree.
+constexpr int RES_ROWS = 4;
+constexpr int RES_KC = 16;
+
+__global__ __launch_bounds__(256) void residual_kernel(const double *__restrict__ x,
+                                                       float *__restrict__ r32,
+                                                       double *__restrict__ partial, GridArgs g)
+{
+    __shared__ double red[256];
+    const int64_t i = 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j0 = 1 + (int64_t)blockIdx.y * RES_ROWS;
+    const int64_t k0 = 1 + (int64_t)blockIdx.z * RES_KC;
+    double acc = 0.0;
+    if (i <= g.nx) {
+        for (int64_t k = k0; k < k0 + RES_KC && k <= g.nz; ++k)
+            for (int64_t j = j0; j < j0 + RES_ROWS && j <= g.ny; ++j) {
+                const int64_t o = i + j * g.sy + k * g.sz;
+                double s = x[o - 1];
+                s = s + x[o + 1];
+                s = s + x[o - g.sy];
+                s = s + x[o + g.sy];
+                s = s + x[o - g.sz];
+                s = s + x[o + g.sz];
+                const double six_x = 6.0 * x[o];
+                const double v = s - six_x;
+                r32[o] = (float)v;
+                acc = acc + v * v;
+            }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partial[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+}
+
+// norm2 = sum of the n partials: each thread sums a strided subset in order,
+// then a fixed tree over the 256 threads
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double *__restrict__ partial,
+                                                           int64_t n, double *__restrict__ norm2)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t t = threadIdx.x; t < n; t += 256)
+        acc = acc + partial[t];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *norm2 = red[0];
+}
+
+// every element (i, j, k) of a grid, shell included, set to v
+template <typename real>
+__global__ __launch_bounds__(256) void grid_fill_kernel(real *__restrict__ x, real v, GridArgs g)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * RES_ROWS;
+    const int64_t k0 = (int64_t)blockIdx.z * RES_KC;
+    if (i > g.nx + 1)
+        return;
+    for (int64_t k = k0; k < k0 + RES_KC && k <= g.nz + 1; ++k)
+        for (int64_t j = j0; j < j0 + RES_ROWS && j <= g.ny + 1; ++j)
+            x[i + j * g.sy + k * g.sz] = v;
+}
+
+// x += (double)e32 on the interior
+__global__ __launch_bounds__(256) void update_kernel(double *__restrict__ x,
+                                                     const float *__restrict__ e32, GridArgs g)
+{
+    const int64_t i = 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j0 = 1 + (int64_t)blockIdx.y * RES_ROWS;
+    const int64_t k0 = 1 + (int64_t)blockIdx.z * RES_KC;
+    if (i > g.nx)
+        return;
+    for (int64_t k = k0; k < k0 + RES_KC && k <= g.nz; ++k)
+        for (int64_t j = j0; j < j0 + RES_ROWS && j <= g.ny; ++j) {
+            const int64_t o = i + j * g.sy + k * g.sz;
+            x[o] = x[o] + (double)e32[o];
+        }
+}
+
 // ------------------------------------------------------ shell face arrays --
 // The six face layers of the shell as one compact array of F values:
 // [i = 0 face: (k, j)], [i = nx+1 face], [j = 0 face: (k, i)], [j = ny+1 face],
@@ -284,6 +380,48 @@ hipError_t launch_copy_shell(const real *a, real *b, const GridArgs &g, hipStrea
     const int64_t n = (g.nx + 2) * (g.ny + 2) + (g.nx + 2) * (g.nz + 2) + (g.ny + 2) * (g.nz + 2);
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(copy_shell_kernel<real>, dim3(blocks), dim3(256), 0, st, a, b, g);
+    return hipGetLastError();
+}
+
+static dim3 strip_grid(const GridArgs &g)
+{
+    return dim3((unsigned)((g.nx + 255) / 256), (unsigned)((g.ny + RES_ROWS - 1) / RES_ROWS),
+                (unsigned)((g.nz + RES_KC - 1) / RES_KC));
+}
+
+int64_t residual_partials(const GridArgs &g)
+{
+    const dim3 d = strip_grid(g);
+    return (int64_t)d.x * d.y * d.z;
+}
+
+hipError_t launch_residual(const double *x, float *r32, double *partial, double *norm2,
+                           const GridArgs &g, hipStream_t st)
+{
+    const dim3 grid = strip_grid(g);
+    hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, st, x, r32, partial, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, partial,
+                       residual_partials(g), norm2);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_grid_fill(real *x, real v, const GridArgs &g, hipStream_t st)
+{
+    const dim3 grid((unsigned)((g.nx + 2 + 255) / 256), (unsigned)((g.ny + 2 + RES_ROWS - 1) / RES_ROWS),
+                    (unsigned)((g.nz + 2 + RES_KC - 1) / RES_KC));
+    hipLaunchKernelGGL(grid_fill_kernel<real>, grid, dim3(256), 0, st, x, v, g);
+    return hipGetLastError();
+}
+template hipError_t launch_grid_fill<float>(float *, float, const GridArgs &, hipStream_t);
+template hipError_t launch_grid_fill<double>(double *, double, const GridArgs &, hipStream_t);
+
+hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStream_t st)
+{
+    hipLaunchKernelGGL(update_kernel, strip_grid(g), dim3(256), 0, st, x, e32, g);
     return hipGetLastError();
 }
 

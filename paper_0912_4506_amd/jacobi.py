@@ -130,3 +130,45 @@ def adjoint(lam_a, lam_b, T, t=None, bx=0, by=0, kchunk=0, ws=None):
                                          _ptr(lam_a), _ptr(lam_b), int(T), ctypes.byref(tile),
                                          _ptr(ws), ws.numel(), _stream(lam_a), ctypes.byref(out)))
     return lam_b if out.value else lam_a
+
+
+def fill(x, value):
+    """Every element of grid x (shell included) set to value."""
+    with torch.cuda.device(x.device):
+        check(_lib.load().jacobi_fill(dtype_code(x), ctypes.byref(grid_of(x)), _ptr(x),
+                                      float(value), _stream(x)))
+    return x
+
+
+def residual_workspace(x):
+    n = _lib.load().jacobi_residual_workspace(ctypes.byref(grid_of(x)))
+    if n == 0:
+        check(_lib.JAC_EARG)
+    return torch.empty(n, dtype=torch.uint8, device=x.device)
+
+
+def residual_f64(x, r32, norm2, ws=None):
+    """r32 <- (float)(b - A x) on the interior (FP64 arithmetic); norm2[0] <-
+    |b - A x|^2 (device float64 tensor of one element)."""
+    if x.dtype != torch.float64 or r32.dtype != torch.float32 or norm2.dtype != torch.float64:
+        raise TypeError("residual_f64 needs float64 x, float32 r32 and a float64 norm2")
+    if x.shape != r32.shape or x.stride() != r32.stride():
+        raise ValueError("x and r32 must share shape and strides")
+    if ws is None:
+        ws = residual_workspace(x)
+    with torch.cuda.device(x.device):
+        check(_lib.load().jacobi_residual_f64(ctypes.byref(grid_of(x)), _ptr(x), _ptr(r32),
+                                              _ptr(norm2), _ptr(ws), ws.numel(), _stream(x)))
+    return norm2
+
+
+def update_f64(x, e32):
+    """x += (double)e32 on the interior."""
+    if x.dtype != torch.float64 or e32.dtype != torch.float32:
+        raise TypeError("update_f64 needs float64 x and float32 e32")
+    if x.shape != e32.shape or x.stride() != e32.stride():
+        raise ValueError("x and e32 must share shape and strides")
+    with torch.cuda.device(x.device):
+        check(_lib.load().jacobi_update_f64(ctypes.byref(grid_of(x)), _ptr(x), _ptr(e32),
+                                            _stream(x)))
+    return x

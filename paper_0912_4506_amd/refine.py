@@ -1,0 +1,81 @@
+"""Mixed-precision Laplace solve: FP64 iterative refinement around FP32
+temporally blocked Jacobi sweeps (a form added on top of the paper's method).
+
+The system is the one whose fixed point the Jacobi update of Sect. 1.1 of the
+paper seeks: A x = b with A = 6I - (interior adjacency) and b = the sum of
+each cell's shell neighbours, i.e. r = b - A x = (six neighbours of x) - 6x
+with the shell of x as Dirichlet data.
+
+Outer loop (on the GPU, FP64):   r = b - A x;  stop if |r| <= tol |r0|;
+Inner solve (on the GPU, FP32):  e = `inner` Jacobi sweeps of A e = r from
+                                 e = 0 (zero shell), t sweeps per pass;
+Update (on the GPU, FP64):       x += e.
+The only host synchronisation per outer iteration reads |r|^2 (8 bytes).
+"""
+import math
+
+import torch
+
+from . import jacobi
+
+
+def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, callback=None):
+    """Solve in place.  x: float64 GPU grid (shell = Dirichlet data, interior
+    = initial guess).  Returns (x, outer_iterations, relative_residual).
+    ``check_every`` > 1 reads the norm only every that many outer iterations
+    (fewer host synchronisations; the stopping point is then a multiple)."""
+    if x.dtype != torch.float64:
+        raise TypeError("x must be float64")
+    r32 = torch.empty(x.shape, dtype=torch.float32, device=x.device)
+    jacobi.fill(r32, 0.0)
+    e_a = torch.empty_like(r32)
+    e_b = torch.empty_like(r32)
+    norm2 = torch.zeros(1, dtype=torch.float64, device=x.device)
+    ws = jacobi.residual_workspace(x)
+    r0 = None
+    rel = float("inf")
+    it = 0
+    while True:
+        jacobi.residual_f64(x, r32, norm2, ws)
+        if it % check_every == 0 or it >= max_outer:
+            n = math.sqrt(norm2.item())
+            if r0 is None:
+                r0 = n if n > 0 else 1.0
+            rel = n / r0
+            if callback is not None:
+                callback(it, rel)
+            if rel <= tol or it >= max_outer:
+                break
+        jacobi.fill(e_a, 0.0)
+        e = jacobi.tblock(e_a, e_b, inner, t=t, rhs=r32)
+        jacobi.update_f64(x, e)
+        it += 1
+    return x, it, rel
+
+
+def jacobi_solve_f64(x, tol=1e-10, check=50, t=8, max_sweeps=10**9, callback=None):
+    """All-FP64 Jacobi (the update of Sect. 1.1) to |r| <= tol |r0|, the
+    residual checked every ``check`` sweeps.  Returns (x, sweeps, rel)."""
+    if x.dtype != torch.float64:
+        raise TypeError("x must be float64")
+    a = x
+    b = torch.empty_like(x)
+    r32 = torch.empty(x.shape, dtype=torch.float32, device=x.device)
+    norm2 = torch.zeros(1, dtype=torch.float64, device=x.device)
+    ws = jacobi.residual_workspace(x)
+    jacobi.residual_f64(a, r32, norm2, ws)
+    r0 = math.sqrt(norm2.item()) or 1.0
+    rel = 1.0
+    sweeps = 0
+    while rel > tol and sweeps < max_sweeps:
+        out = jacobi.tblock(a, b, check, t=t) if t and t > 1 else jacobi.plain(a, b, check)
+        if out is b:
+            a, b = b, a
+        sweeps += check
+        jacobi.residual_f64(a, r32, norm2, ws)
+        rel = math.sqrt(norm2.item()) / r0
+        if callback is not None:
+            callback(sweeps, rel)
+    if a is not x:
+        x.copy_(a)
+    return x, sweeps, rel

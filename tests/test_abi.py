@@ -1,0 +1,114 @@
+"""The C ABI on the CPU: libjacobi.so loads, exports every function
+include/jacobi.h declares, and rejects bad arguments before any HIP call
+(so no GPU is needed)."""
+import ctypes
+
+import pytest
+
+from paper_0912_4506_amd import _lib
+from paper_0912_4506_amd._lib import Grid, Tile, JAC_EARG, JAC_EUNSUPPORTED, JAC_EWORKSPACE
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _lib.declared_symbols()
+    assert len(declared) >= 12
+    missing = [s for s in declared if not hasattr(lib, s)]
+    assert not missing, missing
+    assert set(declared) == set(_lib.SIGNATURES), "binding and header disagree"
+    assert lib.jacobi_version() == 1
+
+
+P = ctypes.c_void_p
+A = P(1 << 20)
+B = P(1 << 30)
+OUT = ctypes.c_int()
+
+
+def err(lib):
+    return lib.jacobi_last_error().decode()
+
+
+def call_plain(lib, g, a=A, b=B, T=3, dtype=1):
+    return lib.jacobi_plain(dtype, ctypes.byref(g) if g is not None else None, a, b, T, None,
+                            ctypes.byref(OUT))
+
+
+def test_grid_checks(lib):
+    assert call_plain(lib, Grid(0, 4, 4, 0, 0)) == JAC_EARG and "extents" in err(lib)
+    assert call_plain(lib, Grid(4, 4, 4, 5, 0)) == JAC_EARG and "sy" in err(lib)
+    assert call_plain(lib, Grid(4, 4, 4, 6, 30)) == JAC_EARG and "sz" in err(lib)
+    assert call_plain(lib, None) == JAC_EARG and "NULL" in err(lib)
+
+
+def test_pointer_and_dtype_checks(lib):
+    g = Grid(4, 4, 4, 0, 0)
+    assert call_plain(lib, g, a=None) == JAC_EARG and "a is NULL" in err(lib)
+    assert call_plain(lib, g, a=P((1 << 20) + 4)) == JAC_EARG and "aligned" in err(lib)
+    assert call_plain(lib, g, b=P((1 << 20) + 8 * 10)) == JAC_EARG and "overlap" in err(lib)
+    assert call_plain(lib, g, dtype=7) == JAC_EARG and "dtype" in err(lib)
+    assert call_plain(lib, g, T=-1) == JAC_EARG and "negative" in err(lib)
+
+
+def test_zero_sweeps_enqueue_nothing(lib):
+    OUT.value = 5
+    assert call_plain(lib, Grid(4, 4, 4, 0, 0), T=0) == 0 and OUT.value == 0
+    assert err(lib) == ""
+
+
+def test_tile_checks(lib):
+    g = Grid(8, 8, 8, 0, 0)
+
+    def tb(tile):
+        return lib.jacobi_tblock(1, ctypes.byref(g), A, B, 5, ctypes.byref(tile), None, None,
+                                 ctypes.byref(OUT))
+
+    assert tb(Tile(9, 0, 0, 0)) == JAC_EARG and "depth" in err(lib)
+    assert tb(Tile(4, 100, 0, 0)) == JAC_EARG
+    assert tb(Tile(4, 100, 100, 0)) == JAC_EUNSUPPORTED and "menu" in err(lib)
+    assert tb(Tile(2, 0, 0, -1)) == JAC_EARG and "kchunk" in err(lib)
+
+
+def test_menu_and_default_tile(lib):
+    buf = (ctypes.c_int * 64)()
+    n = lib.jacobi_tile_menu(1, buf, 32)
+    assert n >= 2
+    pairs = [(buf[2 * m], buf[2 * m + 1]) for m in range(n)]
+    assert all(bx % 64 == 0 and by > 0 for bx, by in pairs)
+    t = Tile()
+    assert lib.jacobi_default_tile(1, ctypes.byref(Grid(512, 512, 512, 0, 0)), 100, 0,
+                                   ctypes.byref(t)) == 0
+    assert 1 <= t.t <= 8 and (t.bx, t.by) in pairs
+    # depth never exceeds the sweep count
+    assert lib.jacobi_default_tile(1, ctypes.byref(Grid(9, 9, 9, 0, 0)), 3, 8, ctypes.byref(t)) == 0
+    assert t.t == 3
+
+
+def test_adjoint_workspace_checks(lib):
+    g = Grid(10, 11, 12, 0, 0)
+    need = lib.jacobi_adjoint_workspace(1, ctypes.byref(g), 4)
+    faces = 2 * (11 * 12 + 10 * 12 + 10 * 11)
+    assert need == (2 + 4) * faces * 8
+    tile = Tile(4, 0, 0, 0)
+    rc = lib.jacobi_adjoint(1, ctypes.byref(g), A, B, 5, ctypes.byref(tile), None, 0, None,
+                            ctypes.byref(OUT))
+    assert rc == JAC_EWORKSPACE
+    rc = lib.jacobi_adjoint(1, ctypes.byref(g), A, B, 5, ctypes.byref(tile), P(1 << 34), need - 8,
+                            None, ctypes.byref(OUT))
+    assert rc == JAC_EWORKSPACE and "needed" in err(lib)
+
+
+def test_residual_and_copy_checks(lib):
+    g = Grid(10, 10, 10, 0, 0)
+    n2 = P(1 << 36)
+    need = lib.jacobi_residual_workspace(ctypes.byref(g))
+    assert need > 0
+    assert lib.jacobi_residual_f64(ctypes.byref(g), A, B, n2, None, 0, None) == JAC_EWORKSPACE
+    assert lib.jacobi_residual_f64(ctypes.byref(g), A, P((1 << 20) + 16), n2, P(1 << 38), need,
+                                   None) == JAC_EARG
+    assert lib.jacobi_copy(A, P((1 << 20) + 16), 64, None) == JAC_EARG   # overlap
+    assert lib.jacobi_copy(A, B, 12, None) == JAC_EARG                   # not a multiple of 16

@@ -1,0 +1,115 @@
+"""GPU parity of the refinement helpers and the mixed-precision solve with
+the CPU oracle (residual, right-hand-side sweeps and the FP64 Jacobi solve,
+pinned on the CPU to dense matrices and a DST-I direct solve)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0912_4506_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(u, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(u)).to("cuda", dtype)
+
+
+@pytest.mark.parametrize("shape", [(30, 17, 23), (300, 5, 9), (1, 1, 1), (257, 40, 20)])
+def test_residual_f64(jac, shape):
+    nx, ny, nz = shape
+    x = inputs.grid(nx, ny, nz, seed=4)
+    r_ref, n2_ref = oracle.residual(x)
+    xt = dev(x)
+    r32 = torch.zeros(xt.shape, dtype=torch.float32, device="cuda")
+    norm2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    jac.residual_f64(xt, r32, norm2)
+    torch.cuda.synchronize()
+    got = r32.cpu().numpy()
+    # the FP64 residual matches the oracle bitwise before the cast to float
+    assert np.array_equal(got[1:-1, 1:-1, 1:-1], r_ref[1:-1, 1:-1, 1:-1].astype(np.float32))
+    # the norm: a different (fixed) summation order
+    assert math.isclose(norm2.item(), n2_ref, rel_tol=1e-12)
+    # deterministic run to run
+    n_first = norm2.item()
+    jac.residual_f64(xt, r32, norm2)
+    assert norm2.item() == n_first
+
+
+def test_update_and_fill(jac):
+    nx, ny, nz = 33, 12, 7
+    x = inputs.grid(nx, ny, nz, seed=2)
+    e = inputs.grid(nx, ny, nz, seed=3, dtype=np.float32)
+    xt, et = dev(x), dev(e, torch.float32)
+    jac.update_f64(xt, et)
+    ref = x.copy()
+    ref[1:-1, 1:-1, 1:-1] += e[1:-1, 1:-1, 1:-1].astype(np.float64)
+    assert np.array_equal(xt.cpu().numpy(), ref)
+    jac.fill(et, 0.0)
+    assert torch.count_nonzero(et).item() == 0
+
+
+@pytest.mark.parametrize("dtype,t", [(torch.float64, 4), (torch.float64, 8), (torch.float32, 8)])
+def test_rhs_sweeps(jac, dtype, t):
+    """jacobi_tblock with rhs from e = 0: FP64 bitwise with the oracle's
+    right-hand-side sweeps; FP32 within 1e-5 of max|e|."""
+    nx, ny, nz, T = 70, 45, 33, 50
+    r = inputs.grid(nx, ny, nz, seed=9)
+    np_dt = np.float64 if dtype == torch.float64 else np.float32
+    r = r.astype(np_dt)
+    ref = oracle.rhs_sweeps(r.astype(np.float64), T)
+    a = torch.zeros(r.shape, dtype=dtype, device="cuda")
+    b = torch.full_like(a, float("nan"))
+    out = jac.tblock(a, b, T, t=t, rhs=dev(r, dtype))
+    got = out.cpu().numpy().astype(np.float64)
+    if dtype == torch.float64:
+        assert np.array_equal(got, ref)
+    else:
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_mixed_solve_matches_fp64_oracle(jac, n):
+    """The FP32-inner / FP64-outer solve reaches |r| <= 1e-10 |r0| as recomputed
+    by the oracle, within one outer iteration (50 sweeps) of the oracle's FP64
+    Jacobi, and agrees with the oracle's solution to the tolerance's bound."""
+    from paper_0912_4506_amd.refine import refine_solve, jacobi_solve_f64
+    g = inputs.laplace_problem(n, n, n, seed=0)
+    x = dev(g)
+    x, outer, rel = refine_solve(x, tol=1e-10, inner=50, t=8)
+    xs = x.cpu().numpy()
+    # the oracle recomputes the final residual
+    r, n2 = oracle.residual(xs)
+    r0, n20 = oracle.residual(g)
+    assert math.sqrt(n2) <= 1.0000001e-10 * math.sqrt(n20)
+    # shell untouched
+    m = np.ones(g.shape, bool)
+    m[1:-1, 1:-1, 1:-1] = False
+    assert np.array_equal(xs[m], g[m])
+    # the oracle's all-FP64 Jacobi, residual checked every 50 sweeps
+    xo, sweeps, rel_o, ok = oracle.jacobi_solve(g, 1e-10, check_every=50)
+    assert ok
+    assert abs(outer * 50 - sweeps) <= 50
+    lam_min = 6 - 6 * math.cos(math.pi / (n + 1))
+    bound = 2e-10 * math.sqrt(n20) / lam_min
+    assert np.max(np.abs(xs - xo)) <= bound
+    # the GPU all-FP64 Jacobi gives the oracle's iterate bitwise at the same sweep count
+    xf = dev(g)
+    xf, sw, rel_f = jacobi_solve_f64(xf, tol=1e-10, check=50, t=8)
+    assert sw == sweeps
+    assert np.array_equal(xf.cpu().numpy(), xo)
+
+
+def test_harmonic_shell_solution(jac):
+    """Dirichlet data from a discrete harmonic polynomial: the solution is the
+    polynomial."""
+    from paper_0912_4506_amd.refine import refine_solve
+    n = 20
+    k, j, i = np.meshgrid(np.arange(n + 2), np.arange(n + 2), np.arange(n + 2), indexing="ij")
+    p = (i * j - 2 * j * k + 3 * i - k + i * j * k / 10.0).astype(np.float64)
+    x0 = p.copy()
+    x0[1:-1, 1:-1, 1:-1] = 0.0
+    x, outer, rel = refine_solve(dev(x0), tol=1e-11)
+    assert np.max(np.abs(x.cpu().numpy() - p)) <= 1e-8 * np.max(np.abs(p))
