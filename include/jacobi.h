@@ -132,6 +132,42 @@ int jacobi_adjoint(int dtype, const jac_grid_t *g, void *lam_a, void *lam_b,
                    int T, const jac_tile_t *tile, void *ws, size_t ws_bytes,
                    void *stream, int *out_idx);
 
+/* Batched runs: many independent grids (each with its own geometry and
+ * sweep count) in one launch.  Two steps, so that the launch needs no host
+ * data and can be captured in a hipGraph and replayed:
+ *  1. jacobi_batched_plan (host only): lays out a plan image in plan_host
+ *     (jacobi_batched_plan_bytes(...) bytes, host memory): per-grid block
+ *     geometry and the list of (grid, pass, block) work items in pass order.
+ *     g, a, b, T: n-entry host arrays (a[m], b[m] device grids of grid m,
+ *     not overlapping each other or any other grid's).  tile: one blocking
+ *     choice for the whole batch (NULL or zero fields = library choice).
+ *     out_idx_host[m] receives where grid m's result will be (0 = a, 1 = b).
+ *  2. The caller copies the image to device memory (plan_dev, 16-byte
+ *     aligned), then jacobi_batched_run enqueues: a shell copy a -> b for
+ *     every grid, then either
+ *       JAC_BATCH_RELAXED: one persistent launch; workgroups take work items
+ *         in order and wait, through one counter per block, until the
+ *         neighbouring blocks of the same grid finished the previous pass
+ *         (the lower-bound condition of the relaxed synchronisation of
+ *         Sect. 1.3, Eq. 3, per block instead of per thread), or
+ *       JAC_BATCH_LOCKSTEP: one launch per pass (a global barrier between
+ *         passes, the scheme relaxed synchronisation replaces).
+ *     ws: device workspace of jacobi_batched_workspace(plan_host) bytes
+ *     (the counters; reset by the run itself, every run).  Its last int is
+ *     an error flag: a relaxed-mode wait that has not ended after about
+ *     2^20 polls gives up and sets it to 1, and every workgroup then stops
+ *     (results are invalid); the caller may read it after synchronising.  plan_host must be the image
+ *     plan_dev was copied from. */
+enum { JAC_BATCH_RELAXED = 0, JAC_BATCH_LOCKSTEP = 1 };
+size_t jacobi_batched_plan_bytes(int dtype, int n, const jac_grid_t *g,
+                                 const int *T, const jac_tile_t *tile);
+int jacobi_batched_plan(int dtype, int n, const jac_grid_t *g, void *const *a,
+                        void *const *b, const int *T, const jac_tile_t *tile,
+                        void *plan_host, size_t plan_bytes, int *out_idx_host);
+size_t jacobi_batched_workspace(const void *plan_host);
+int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws,
+                       size_t ws_bytes, int mode, void *stream);
+
 /* Mixed-precision refinement helpers (outer FP64 loop around an FP32 Jacobi
  * inner solve; the refinement is not in the paper, the operator is the
  * Laplace system whose fixed point the Jacobi iteration of Sect. 1.1 seeks).

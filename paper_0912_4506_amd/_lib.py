@@ -15,6 +15,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "jacobi.h")
 JAC_F32, JAC_F64 = 0, 1
 JAC_OK, JAC_EARG, JAC_EHIP, JAC_EWORKSPACE, JAC_EUNSUPPORTED = 0, -1, -2, -3, -4
 MAX_DEPTH = 8
+JAC_BATCH_RELAXED, JAC_BATCH_LOCKSTEP = 0, 1
 
 
 class Grid(ctypes.Structure):
@@ -53,6 +54,11 @@ SIGNATURES = {
     "jacobi_update_f64": ([_GP, _P, _P, _P], ctypes.c_int),
     "jacobi_fill": ([ctypes.c_int, _GP, _P, ctypes.c_double, _P], ctypes.c_int),
     "jacobi_copy": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "jacobi_batched_plan_bytes": ([ctypes.c_int, ctypes.c_int, _GP, _IP, _TP], ctypes.c_size_t),
+    "jacobi_batched_plan": ([ctypes.c_int, ctypes.c_int, _GP, ctypes.POINTER(_P),
+                             ctypes.POINTER(_P), _IP, _TP, _P, ctypes.c_size_t, _IP], ctypes.c_int),
+    "jacobi_batched_workspace": ([_P], ctypes.c_size_t),
+    "jacobi_batched_run": ([_P, _P, _P, ctypes.c_size_t, ctypes.c_int, _P], ctypes.c_int),
     "jacobi_tile_menu": ([ctypes.c_int, _IP, ctypes.c_int], ctypes.c_int),
     "jacobi_default_tile": ([ctypes.c_int, _GP, ctypes.c_int, ctypes.c_int, _TP], ctypes.c_int),
 }

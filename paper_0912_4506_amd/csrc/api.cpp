@@ -350,6 +350,51 @@ int run_adjoint(const Geo &g, real *la, real *lb, int T, const jac_tile_t &tile,
     return JAC_OK;
 }
 
+// ---------------------------------------------------------- batched plans --
+size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+struct BatchSizes {
+    int nitems = 0, ntiles = 0, maxpasses = 0;
+};
+
+// Per-grid plan of a batched run; false with the error set on failure.
+struct GridPlan {
+    Geo geo;
+    TbPlan tp;
+    int passes, tiles;
+};
+
+int plan_batch_grid(const jac_grid_t *g, int T, const jac_tile_t &tile, GridPlan *gp, int idx)
+{
+    int rc;
+    if ((rc = check_grid(g, &gp->geo)))
+        return fail(rc, "grid %d: %s", idx, jacobi_last_error());
+    if (T < 0)
+        return fail(JAC_EARG, "grid %d: T = %d is negative", idx, T);
+    const jac::TileShape *shape = find_shape(tile.bx, tile.by);
+    const int t = tile.t;
+    if (!plan_ij(gp->geo, *shape, t, &gp->tp))
+        return fail(JAC_EUNSUPPORTED, "block %d x %d has no valid cells at depth %d", tile.bx, tile.by, t);
+    // a block's neighbours of the previous pass are the adjacent blocks only
+    // when every valid width is at least the halo
+    if (shape->bx() - 2 * gp->tp.hi < gp->tp.hi || shape->by() - 2 * t < t)
+        return fail(JAC_EUNSUPPORTED, "block %d x %d is too small for depth %d in a batch", tile.bx,
+                    tile.by, t);
+    int64_t kc = tile.kchunk > 0 ? tile.kchunk : (gp->geo.nz <= 128 ? gp->geo.nz : 64);
+    kc = std::max<int64_t>(kc, t);
+    kc = std::min<int64_t>(kc, gp->geo.nz);
+    gp->tp.kchunk = (int)kc;
+    gp->tp.nkc = (int)((gp->geo.nz + kc - 1) / kc);
+    if (gp->tp.nkc > 1 && gp->tp.kchunk < t)
+        return fail(JAC_EUNSUPPORTED, "k chunk shorter than the depth");
+    const int64_t tiles = (int64_t)gp->tp.nti * gp->tp.ntj * gp->tp.nkc;
+    if (tiles > (1 << 24))
+        return fail(JAC_EUNSUPPORTED, "grid %d needs too many blocks", idx);
+    gp->tiles = (int)tiles;
+    gp->passes = (T + t - 1) / t;
+    return JAC_OK;
+}
+
 int check_pair(int dtype, const Geo &g, const void *a, const void *b)
 {
     int rc;
@@ -572,6 +617,237 @@ int jacobi_fill(int dtype, const jac_grid_t *g, void *x, double value, void *str
                        : jac::launch_grid_fill<float>((float *)x, (float)value, grid_args(geo),
                                                       (hipStream_t)stream);
     return e == hipSuccess ? JAC_OK : hip_fail(e, "fill launch");
+}
+
+static int batch_common(int dtype, int n, const jac_grid_t *g, const int *T, const jac_tile_t *tile,
+                        jac_tile_t *tl, GridPlan **plans_out, BatchSizes *bs)
+{
+    int rc;
+    if ((rc = check_dtype(dtype)))
+        return rc;
+    if (n < 1 || n > 65535)
+        return fail(JAC_EARG, "batch size n = %d outside 1..65535", n);
+    if (!g || !T)
+        return fail(JAC_EARG, "grid or T array is NULL");
+    int Tmax = 0;
+    for (int m = 0; m < n; ++m)
+        Tmax = std::max(Tmax, T[m]);
+    if ((rc = resolve_tile(dtype, tile, Tmax, tl)))
+        return rc;
+    if (tl->t < 1)
+        tl->t = 1;
+    GridPlan *plans = new GridPlan[n];
+    BatchSizes z;
+    for (int m = 0; m < n; ++m) {
+        if ((rc = plan_batch_grid(&g[m], T[m], *tl, &plans[m], m))) {
+            delete[] plans;
+            return rc;
+        }
+        if ((int64_t)z.nitems + (int64_t)plans[m].passes * plans[m].tiles > INT_MAX / 2 ||
+            (int64_t)z.ntiles + plans[m].tiles > INT_MAX / 2) {
+            delete[] plans;
+            return fail(JAC_EUNSUPPORTED, "batch too large");
+        }
+        z.nitems += plans[m].passes * plans[m].tiles;
+        z.ntiles += plans[m].tiles;
+        z.maxpasses = std::max(z.maxpasses, plans[m].passes);
+    }
+    *plans_out = plans;
+    *bs = z;
+    return JAC_OK;
+}
+
+static size_t batch_image_bytes(int n, const BatchSizes &z)
+{
+    return align16(sizeof(jac::BatchHeader)) + align16((size_t)n * sizeof(jac::BatchGrid)) +
+           align16((size_t)z.nitems * sizeof(jac::BatchItem)) +
+           align16((size_t)(z.maxpasses + 1) * sizeof(int));
+}
+
+size_t jacobi_batched_plan_bytes(int dtype, int n, const jac_grid_t *g, const int *T,
+                                 const jac_tile_t *tile)
+{
+    g_err.clear();
+    jac_tile_t tl;
+    GridPlan *plans = nullptr;
+    BatchSizes z;
+    if (batch_common(dtype, n, g, T, tile, &tl, &plans, &z))
+        return 0;
+    delete[] plans;
+    return batch_image_bytes(n, z);
+}
+
+int jacobi_batched_plan(int dtype, int n, const jac_grid_t *g, void *const *a, void *const *b,
+                        const int *T, const jac_tile_t *tile, void *plan_host, size_t plan_bytes,
+                        int *out_idx_host)
+{
+    g_err.clear();
+    jac_tile_t tl;
+    GridPlan *plans = nullptr;
+    BatchSizes z;
+    int rc;
+    if ((rc = batch_common(dtype, n, g, T, tile, &tl, &plans, &z)))
+        return rc;
+    auto done = [&](int code) {
+        delete[] plans;
+        return code;
+    };
+    if (!a || !b || !plan_host || !out_idx_host)
+        return done(fail(JAC_EARG, "a, b, plan_host and out_idx_host must not be NULL"));
+    const size_t need = batch_image_bytes(n, z);
+    if (plan_bytes < need)
+        return done(fail(JAC_EWORKSPACE, "plan buffer has %zu bytes, %zu needed", plan_bytes, need));
+    const size_t es = elem_size(dtype);
+    for (int m = 0; m < n; ++m) {
+        if ((rc = check_pair(dtype, plans[m].geo, a[m], b[m])))
+            return done(fail(rc, "grid %d: %s", m, jacobi_last_error()));
+    }
+    for (int m = 0; m < n; ++m)
+        for (int q = m + 1; q < n; ++q) {
+            const size_t bm = (size_t)plans[m].geo.span * es, bq = (size_t)plans[q].geo.span * es;
+            if (overlap(a[m], bm, a[q], bq) || overlap(a[m], bm, b[q], bq) ||
+                overlap(b[m], bm, a[q], bq) || overlap(b[m], bm, b[q], bq))
+                return done(fail(JAC_EARG, "grids %d and %d overlap", m, q));
+        }
+    unsigned char *img = (unsigned char *)plan_host;
+    memset(img, 0, need);
+    jac::BatchHeader h;
+    memset(&h, 0, sizeof h);
+    h.magic = jac::BATCH_MAGIC;
+    h.dtype = dtype;
+    h.n = n;
+    h.nitems = z.nitems;
+    h.ntiles = z.ntiles;
+    h.cfg = find_shape(tl.bx, tl.by)->id;
+    h.t = tl.t;
+    h.maxpasses = z.maxpasses;
+    h.grids_off = (int64_t)align16(sizeof(jac::BatchHeader));
+    h.items_off = h.grids_off + (int64_t)align16((size_t)n * sizeof(jac::BatchGrid));
+    h.pass_off = h.items_off + (int64_t)align16((size_t)z.nitems * sizeof(jac::BatchItem));
+    h.total_bytes = (int64_t)need;
+    jac::BatchGrid *grids = (jac::BatchGrid *)(img + h.grids_off);
+    jac::BatchItem *items = (jac::BatchItem *)(img + h.items_off);
+    int *pass_start = (int *)(img + h.pass_off);
+    int off = 0;
+    for (int m = 0; m < n; ++m) {
+        const GridPlan &gp = plans[m];
+        jac::BatchGrid &G = grids[m];
+        G.a = a[m];
+        G.b = b[m];
+        G.sy = gp.geo.sy;
+        G.sz = gp.geo.sz;
+        G.nx = (int)gp.geo.nx;
+        G.ny = (int)gp.geo.ny;
+        G.nz = (int)gp.geo.nz;
+        G.nti = gp.tp.nti;
+        G.ntj = gp.tp.ntj;
+        G.nkc = gp.tp.nkc;
+        G.hi = gp.tp.hi;
+        G.kchunk = gp.tp.kchunk;
+        G.T = T[m];
+        G.passes = gp.passes;
+        G.tiles = gp.tiles;
+        G.counter_off = off;
+        off += gp.tiles;
+        out_idx_host[m] = gp.passes % 2;
+        const int64_t sh = (gp.geo.nx + 2) * (gp.geo.ny + 2) + (gp.geo.nx + 2) * (gp.geo.nz + 2) +
+                           (gp.geo.ny + 2) * (gp.geo.nz + 2);
+        h.max_shell = std::max<int64_t>(h.max_shell, sh);
+    }
+    int it = 0;
+    for (int pass = 0; pass < z.maxpasses; ++pass) {
+        pass_start[pass] = it;
+        for (int m = 0; m < n; ++m) {
+            if (pass >= plans[m].passes)
+                continue;
+            for (int tile_i = 0; tile_i < plans[m].tiles; ++tile_i)
+                items[it++] = jac::BatchItem{m, pass, tile_i, 0};
+        }
+    }
+    pass_start[z.maxpasses] = it;
+    memcpy(img, &h, sizeof h);
+    return done(JAC_OK);
+}
+
+static int read_header(const void *plan_host, jac::BatchHeader *h)
+{
+    if (!plan_host)
+        return fail(JAC_EARG, "plan_host is NULL");
+    memcpy(h, plan_host, sizeof *h);
+    if (h->magic != jac::BATCH_MAGIC || (h->dtype != JAC_F32 && h->dtype != JAC_F64) || h->n < 1)
+        return fail(JAC_EARG, "plan_host is not a batch plan");
+    return JAC_OK;
+}
+
+size_t jacobi_batched_workspace(const void *plan_host)
+{
+    g_err.clear();
+    jac::BatchHeader h;
+    if (read_header(plan_host, &h))
+        return 0;
+    return (size_t)(h.ntiles + 2) * sizeof(int);
+}
+
+int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws, size_t ws_bytes,
+                       int mode, void *stream)
+{
+    g_err.clear();
+    jac::BatchHeader h;
+    int rc;
+    if ((rc = read_header(plan_host, &h)))
+        return rc;
+    if (!plan_dev || (uintptr_t)plan_dev % 16)
+        return fail(JAC_EARG, "plan_dev must be a 16-byte aligned device copy of the plan");
+    if (mode != JAC_BATCH_RELAXED && mode != JAC_BATCH_LOCKSTEP)
+        return fail(JAC_EARG, "mode must be JAC_BATCH_RELAXED or JAC_BATCH_LOCKSTEP");
+    const size_t need = (size_t)(h.ntiles + 2) * sizeof(int);
+    if (!ws || ws_bytes < need)
+        return fail(JAC_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    if ((uintptr_t)ws % 4)
+        return fail(JAC_EARG, "workspace is not 4-byte aligned");
+    if (overlap(ws, need, plan_dev, (size_t)h.total_bytes))
+        return fail(JAC_EARG, "workspace overlaps the plan");
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned char *dimg = (const unsigned char *)plan_dev;
+    const jac::BatchGrid *grids = (const jac::BatchGrid *)(dimg + h.grids_off);
+    const jac::BatchItem *items = (const jac::BatchItem *)(dimg + h.items_off);
+    const int *pass_start = (const int *)((const unsigned char *)plan_host + h.pass_off);
+    hipError_t e = h.dtype == JAC_F64 ? jac::launch_batch_shells<double>(grids, h.n, h.max_shell, st)
+                                      : jac::launch_batch_shells<float>(grids, h.n, h.max_shell, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "batch shell copy");
+    if (h.nitems == 0)
+        return JAC_OK;
+    jac::BatchLaunch L;
+    L.grids = grids;
+    L.items = items;
+    L.counters = (int *)ws;
+    L.error = (int *)ws + h.ntiles + 1;
+    L.spin_limit = 1 << 20;
+    if (mode == JAC_BATCH_RELAXED) {
+        if ((e = jac::launch_zero_ints((int *)ws, h.ntiles + 2, st)) != hipSuccess)
+            return hip_fail(e, "counter reset");
+        const DeviceFacts dev = device_facts();
+        int occ = jac::batched_occupancy(h.dtype, h.cfg, h.t);
+        if (occ < 1)
+            occ = 1;
+        L.begin = 0;
+        L.end = h.nitems;
+        L.persistent = 1;
+        e = jac::launch_batched(h.dtype, h.cfg, h.t, L, std::min(h.nitems, dev.cus * occ), st);
+        if (e != hipSuccess)
+            return hip_fail(e, "batched launch");
+    } else {
+        for (int pass = 0; pass < h.maxpasses; ++pass) {
+            L.begin = pass_start[pass];
+            L.end = pass_start[pass + 1];
+            L.persistent = 0;
+            if (L.end > L.begin &&
+                (e = jac::launch_batched(h.dtype, h.cfg, h.t, L, L.end - L.begin, st)) != hipSuccess)
+                return hip_fail(e, "batched pass launch");
+        }
+    }
+    return JAC_OK;
 }
 
 int jacobi_copy(void *dst, const void *src, size_t bytes, void *stream)

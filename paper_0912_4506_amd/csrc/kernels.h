@@ -61,6 +61,47 @@ KernInfo tb_info_rhs_f32(int cfg, int depth);
 KernInfo tb_info_trace_f64(int cfg, int depth);
 KernInfo tb_info_trace_f32(int cfg, int depth);
 
+// ------------------------------------------------------------- batched runs --
+// Plan image of a batched run (built on the host, uploaded by the caller):
+// [BatchHeader][BatchGrid x n][BatchItem x nitems][int pass_start x (maxpasses+1)]
+constexpr uint32_t BATCH_MAGIC = 0x4a414342u;  // "JACB"
+
+struct BatchHeader {
+    uint32_t magic;
+    int dtype, n, nitems, ntiles, cfg, t, maxpasses;
+    int64_t grids_off, items_off, pass_off, total_bytes, max_shell;
+};
+
+struct BatchGrid {
+    const void *a;
+    void *b;
+    int64_t sy, sz;
+    int nx, ny, nz;
+    int nti, ntj, nkc, hi, kchunk;
+    int T, passes, tiles, counter_off;
+};
+
+// One block of one pass of one grid.  Items are ordered pass by pass.
+struct BatchItem {
+    int grid, pass, tile, pad;
+};
+
+// Persistent (relaxed) mode: blocks pop items in order and wait for the
+// neighbouring blocks of the previous pass through per-block counters.
+// Lockstep mode: one launch per pass, one item per workgroup.
+KernInfo batch_info_f64(int cfg, int depth);
+KernInfo batch_info_f32(int cfg, int depth);
+
+struct BatchLaunch {
+    const BatchGrid *grids;
+    const BatchItem *items;
+    int begin, end;      // item range of this launch
+    int *counters;       // [0] next item, [1 + c] pass counter of block c
+    int *error;          // set to 1 when a wait gives up
+    int persistent;
+    int spin_limit;      // polls before a wait gives up
+};
+
 struct TileShape {
     int id, ci, rows, waves;
     int bx() const { return 64 * ci; }
@@ -74,6 +115,10 @@ hipError_t launch_tblock(int cfg, int depth, int mode, const TbArgs<real> &p, in
                          hipStream_t st);
 template <typename real>
 hipError_t launch_copy_shell(const real *a, real *b, const GridArgs &g, hipStream_t st);
+// Shell copy a -> b of every grid of a batch, and a counter reset (n ints = 0).
+template <typename real>
+hipError_t launch_batch_shells(const BatchGrid *grids, int n, int64_t max_shell, hipStream_t st);
+hipError_t launch_zero_ints(int *x, int64_t n, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 // Shell-face helpers of the adjoint (FACES_*): save grid faces into G, zero
 // the grid's faces, clear S, accumulate S += trace levels in order, or write
@@ -90,6 +135,10 @@ hipError_t launch_residual(const double *x, float *r32, double *partial, double 
 template <typename real>
 hipError_t launch_grid_fill(real *x, real v, const GridArgs &g, hipStream_t st);
 hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStream_t st);
+
+hipError_t launch_batched(int dtype, int cfg, int depth, const BatchLaunch &L, int nblocks,
+                          hipStream_t st);
+int batched_occupancy(int dtype, int cfg, int depth);
 
 // Resident workgroups per CU of a tblock instance (0 when it cannot launch).
 int tblock_occupancy(int dtype, int cfg, int depth, int mode);

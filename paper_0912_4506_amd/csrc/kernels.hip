@@ -309,6 +309,44 @@ __global__ void face_finalize_kernel(real *__restrict__ grid, const real *__rest
         grid[face_offset(f, g)] = G[f] + div6(S[f]);
 }
 
+// Shell copy a -> b of every grid of a batch: blockIdx.y is the grid.
+template <typename real>
+__global__ void batch_shell_kernel(const BatchGrid *__restrict__ grids)
+{
+    const BatchGrid G = grids[blockIdx.y];
+    const GridArgs g{G.nx, G.ny, G.nz, G.sy, G.sz};
+    const real *a = (const real *)G.a;
+    real *b = (real *)G.b;
+    const int64_t nxp = g.nx + 2, nyp = g.ny + 2, nzp = g.nz + 2;
+    const int64_t nk = nxp * nyp, nj = nxp * nzp, ni = nyp * nzp;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nk + nj + ni;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t o0, o1;
+        if (t < nk) {
+            const int64_t i = t % nxp, j = t / nxp;
+            o0 = i + j * g.sy;
+            o1 = o0 + (g.nz + 1) * g.sz;
+        } else if (t < nk + nj) {
+            const int64_t u = t - nk, i = u % nxp, k = u / nxp;
+            o0 = i + k * g.sz;
+            o1 = o0 + (g.ny + 1) * g.sy;
+        } else {
+            const int64_t u = t - nk - nj, j = u % nyp, k = u / nyp;
+            o0 = j * g.sy + k * g.sz;
+            o1 = o0 + (g.nx + 1);
+        }
+        b[o0] = a[o0];
+        b[o1] = a[o1];
+    }
+}
+
+__global__ void zero_ints_kernel(int *__restrict__ x, int64_t n)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        x[t] = 0;
+}
+
 // dst = src for bytes/16 16-byte words (grid-stride, coalesced)
 __global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src,
                                                    uint4 *__restrict__ dst, int64_t n)
@@ -360,6 +398,37 @@ hipError_t launch_tblock(int cfg, int depth, int mode, const TbArgs<real> &p, in
     if (e != hipSuccess)
         return e;
     return hipGetLastError();
+}
+
+hipError_t launch_batched(int dtype, int cfg, int depth, const BatchLaunch &L, int nblocks,
+                          hipStream_t st)
+{
+    const KernInfo ki = dtype == 1 ? batch_info_f64(cfg, depth) : batch_info_f32(cfg, depth);
+    if (!ki.fn)
+        return hipErrorInvalidValue;
+    if (ki.lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(ki.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)ki.lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    BatchLaunch arg = L;
+    void *args[] = {&arg};
+    hipError_t e = hipLaunchKernel(ki.fn, dim3(nblocks), dim3(ki.threads), args, ki.lds, st);
+    if (e != hipSuccess)
+        return e;
+    return hipGetLastError();
+}
+
+int batched_occupancy(int dtype, int cfg, int depth)
+{
+    const KernInfo ki = dtype == 1 ? batch_info_f64(cfg, depth) : batch_info_f32(cfg, depth);
+    if (!ki.fn)
+        return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ki.fn, ki.threads, ki.lds) != hipSuccess)
+        return 0;
+    return n;
 }
 
 int tblock_occupancy(int dtype, int cfg, int depth, int mode)
@@ -454,6 +523,22 @@ hipError_t launch_faces(int op, real *grid, real *G, real *S, const real *tr, co
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_batch_shells(const BatchGrid *grids, int n, int64_t max_shell, hipStream_t st)
+{
+    const int bx = (int)std::max<int64_t>(1, std::min<int64_t>((max_shell + 255) / 256, 64));
+    hipLaunchKernelGGL(batch_shell_kernel<real>, dim3(bx, n), dim3(256), 0, st, grids);
+    return hipGetLastError();
+}
+template hipError_t launch_batch_shells<float>(const BatchGrid *, int, int64_t, hipStream_t);
+template hipError_t launch_batch_shells<double>(const BatchGrid *, int, int64_t, hipStream_t);
+
+hipError_t launch_zero_ints(int *x, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(n)), dim3(256), 0, st, x, n);
     return hipGetLastError();
 }
 

@@ -1,0 +1,11 @@
+// Instances of the batched (persistent or lockstep) pass: float.
+#include "tblock.h"
+
+namespace jac {
+
+KernInfo batch_info_f32(int cfg, int depth)
+{
+    return batch_info<float>(cfg, depth);
+}
+
+}  // namespace jac

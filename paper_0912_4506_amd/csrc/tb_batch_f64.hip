@@ -1,0 +1,11 @@
+// Instances of the batched (persistent or lockstep) pass: double.
+#include "tblock.h"
+
+namespace jac {
+
+KernInfo batch_info_f64(int cfg, int depth)
+{
+    return batch_info<double>(cfg, depth);
+}
+
+}  // namespace jac

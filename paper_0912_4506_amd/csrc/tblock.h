@@ -88,26 +88,23 @@ constexpr size_t xch_bytes()
 // Loads clamp their coordinates into the array: cells outside it hold
 // garbage that only ever reaches other outside cells or shell cells, and
 // shell cells (i, j or k = 0 or n+1) pass their value through at every level.
+// One block (ti, tj, tk) of one pass at `depth` <= TL levels (the block
+// geometry is planned for TL; fewer levels leave the valid region valid).
+// xch: the block's LDS exchange buffer.
 template <typename real, int TL, int CI, int R, int W, int MODE>
-__global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
+__device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, int tk, int depth,
+                                        real *xch)
 {
     static_assert(TL >= 1 && TL <= JAC_MAX_DEPTH_DEV, "depth");
-    extern __shared__ unsigned char smem_raw[];
-    real *xch = reinterpret_cast<real *>(smem_raw);  // [2][W][2][TL][CI][64]
-
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    const int bid = xcd_remap(blockIdx.x, p.nti * p.ntj * p.nkc);
-    const int ti = bid % p.nti;
-    const int tj = (bid / p.nti) % p.ntj;
-    const int tk = bid / (p.nti * p.ntj);
     const AxisTile xi = axis_tile(ti, p.nx, 64 * CI, p.hi);
     const AxisTile xj = axis_tile(tj, p.ny, W * R, TL);
     const int k0 = 1 + tk * p.kchunk;
     const int k1 = min(k0 + p.kchunk, p.nz + 1);
-    const int kstart = max(k0 - TL, 0);
-    const int nsteps = ((k1 - 1 + TL) - kstart + 2) & ~1;  // rounded up to even
+    const int kstart = max(k0 - depth, 0);
+    const int nsteps = ((k1 - 1 + depth) - kstart + 2) & ~1;  // rounded up to even
 
     // per-lane columns
     int ic[CI];
@@ -289,6 +286,8 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
         const real *xold = xch + (DBUF ? (par ^ 1) : 0) * XSLAB;
 #pragma unroll
         for (int s = 1; s <= TL; ++s) {
+            if (s > depth)
+                break;
             const int plane = k - s;
             real o[R][CI];
 #pragma unroll
@@ -326,13 +325,13 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
                             o[r][c] = qin(r, c);
                     }
             }
-            if (s < TL) {
+            if (s < depth) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
 #pragma unroll
                     for (int c = 0; c < CI; ++c)
-                        Qo[s][r][c] = o[r][c];
-                trace_level(s, plane, Qo[s]);
+                        Qo[s < TL ? s : 0][r][c] = o[r][c];
+                trace_level(s, plane, Qo[s < TL ? s : 0]);
             } else if (plane >= k0 && plane < k1) {
                 real *dplane = p.dst + (int64_t)plane * p.sz;
 #pragma unroll
@@ -379,8 +378,10 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
         for (int s = 0; s < TL; ++s)
 #pragma unroll
             for (int c = 0; c < CI; ++c) {
-                xcur[xidx(w, 0, s, c, lane)] = Qo[s][0][c];
-                xcur[xidx(w, 1, s, c, lane)] = Qo[s][R - 1][c];
+                if (s < depth) {
+                    xcur[xidx(w, 0, s, c, lane)] = Qo[s][0][c];
+                    xcur[xidx(w, 1, s, c, lane)] = Qo[s][R - 1][c];
+                }
             }
         __syncthreads();
         auto dprev = [&](int side, int s, int c) -> real {
@@ -391,6 +392,8 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
         };
 #pragma unroll
         for (int s = 0; s < TL; ++s) {
+            if (s >= depth)
+                break;
             real west[CI], east[CI];
             neighbours_i(Qo[s][0], west, east);
 #pragma unroll
@@ -420,6 +423,148 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
         step(kstart + n, QA, QB, CA, CB);
         step(kstart + n + 1, QB, QA, CB, CA);
     }
+}
+
+template <typename real, int TL, int CI, int R, int W, int MODE>
+__global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
+{
+    extern __shared__ unsigned char smem_raw[];
+    real *xch = reinterpret_cast<real *>(smem_raw);  // [parity][W][2][TL][CI][64]
+    const int bid = xcd_remap(blockIdx.x, p.nti * p.ntj * p.nkc);
+    const int ti = bid % p.nti;
+    const int tj = (bid / p.nti) % p.ntj;
+    const int tk = bid / (p.nti * p.ntj);
+    tb_tile<real, TL, CI, R, W, MODE>(p, ti, tj, tk, TL, xch);
+}
+
+// Batched pass over many grids (items of the plan).  In persistent mode each
+// workgroup pops items in order; an item of pass p first waits until every
+// neighbouring block (the 3 x 3 x 3 blocks around it, itself included) of
+// the same grid has finished pass p-1.  That one lower-bound condition both
+// guarantees that the level-0 data it reads are written (read after write)
+// and that the neighbours have finished reading the buffer it overwrites
+// (write after read): the lower-bound half of the relaxed synchronisation of
+// Sect. 1.3 (Eq. 3), with a per-block counter in place of a per-thread one.
+// Items are handed out in pass order and a block waits only on items handed
+// out before its own, all held by running blocks, so the waits always end.
+template <typename real, int TL, int CI, int R, int W>
+__global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
+{
+    extern __shared__ unsigned char smem_raw[];
+    real *xch = reinterpret_cast<real *>(smem_raw);
+    __shared__ int item_s, stop_s;
+    int it = L.begin + (int)blockIdx.x;
+    for (;;) {
+        if (L.persistent) {
+            // thread 0 decides for the whole workgroup: the next item, and
+            // whether a wait somewhere gave up (then stop taking work)
+            if (threadIdx.x == 0) {
+                item_s = L.begin + atomicAdd(&L.counters[0], 1);
+                stop_s = __hip_atomic_load(L.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+            it = item_s;
+            const int stop = stop_s;
+            __syncthreads();
+            if (stop)
+                break;
+        }
+        if (it >= L.end)
+            break;
+        const BatchItem m = L.items[it];
+        const BatchGrid G = L.grids[m.grid];
+        const int ti = m.tile % G.nti;
+        const int tj = (m.tile / G.nti) % G.ntj;
+        const int tk = m.tile / (G.nti * G.ntj);
+        int *cnt = L.counters + 1 + G.counter_off;
+        if (L.persistent && m.pass > 0) {
+            if (threadIdx.x == 0) {
+                for (int dk = -1; dk <= 1; ++dk)
+                    for (int dj = -1; dj <= 1; ++dj)
+                        for (int di = -1; di <= 1; ++di) {
+                            const int a = ti + di, b = tj + dj, c = tk + dk;
+                            if (a < 0 || a >= G.nti || b < 0 || b >= G.ntj || c < 0 || c >= G.nkc)
+                                continue;
+                            const int *q = cnt + (c * G.ntj + b) * G.nti + a;
+                            // bounded wait (seconds): a wait that cannot end
+                            // raises the error flag instead of hanging
+                            int spins = 0;
+                            while (__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                                   m.pass) {
+                                __builtin_amdgcn_s_sleep(2);
+                                if (++spins > L.spin_limit ||
+                                    __hip_atomic_load(L.error, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)) {
+                                    __hip_atomic_store(L.error, 1, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                                    break;
+                                }
+                            }
+                        }
+            }
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        TbArgs<real> p;
+        p.src = (const real *)((m.pass % 2 == 0) ? G.a : (const void *)G.b);
+        p.dst = (real *)((m.pass % 2 == 0) ? G.b : (void *)G.a);
+        p.rhs = nullptr;
+        p.trace = nullptr;
+        p.sy = G.sy;
+        p.sz = G.sz;
+        p.nx = G.nx;
+        p.ny = G.ny;
+        p.nz = G.nz;
+        p.nti = G.nti;
+        p.ntj = G.ntj;
+        p.nkc = G.nkc;
+        p.hi = G.hi;
+        p.fstride = 0;
+        p.kchunk = G.kchunk;
+        const int depth = G.T / G.passes + (m.pass < G.T % G.passes ? 1 : 0);
+        tb_tile<real, TL, CI, R, W, MODE_PLAIN>(p, ti, tj, tk, depth, xch);
+        if (!L.persistent)
+            break;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(cnt + m.tile, m.pass + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <typename real, int TL, int CI, int R, int W>
+static KernInfo batch_info_one()
+{
+    return KernInfo{(const void *)batched_kernel<real, TL, CI, R, W>, xch_bytes<real, TL, CI, W>(),
+                    64 * W};
+}
+
+template <typename real, int CI, int R, int W>
+static KernInfo batch_info_depth(int depth)
+{
+    switch (depth) {
+    case 1: return batch_info_one<real, 1, CI, R, W>();
+    case 2: return batch_info_one<real, 2, CI, R, W>();
+    case 3: return batch_info_one<real, 3, CI, R, W>();
+    case 4: return batch_info_one<real, 4, CI, R, W>();
+    case 5: return batch_info_one<real, 5, CI, R, W>();
+    case 6: return batch_info_one<real, 6, CI, R, W>();
+    case 7: return batch_info_one<real, 7, CI, R, W>();
+    case 8: return batch_info_one<real, 8, CI, R, W>();
+    default: return KernInfo{nullptr, 0, 0};
+    }
+}
+
+template <typename real>
+static KernInfo batch_info(int cfg, int depth)
+{
+#define JAC_CFG(ID, CI, R, W) \
+    case ID: return batch_info_depth<real, CI, R, W>(depth);
+    switch (cfg) {
+        JAC_TILE_MENU(JAC_CFG)
+    default: return KernInfo{nullptr, 0, 0};
+    }
+#undef JAC_CFG
 }
 
 template <typename real, int TL, int CI, int R, int W, int MODE>

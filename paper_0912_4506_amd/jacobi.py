@@ -172,3 +172,64 @@ def update_f64(x, e32):
         check(_lib.load().jacobi_update_f64(ctypes.byref(grid_of(x)), _ptr(x), _ptr(e32),
                                             _stream(x)))
     return x
+
+
+class BatchPlan:
+    """A batched run over independent grids (one blocking choice for all).
+
+    Builds the plan image on the host (jacobi_batched_plan), keeps a device
+    copy and the counter workspace, and enqueues the run with run(); run()
+    makes no host copies and allocates nothing, so it can be captured in a
+    CUDA/HIP graph and replayed.  results() names, per grid, the tensor that
+    holds level T after a run."""
+
+    MODES = {"relaxed": _lib.JAC_BATCH_RELAXED, "lockstep": _lib.JAC_BATCH_LOCKSTEP}
+
+    def __init__(self, grids_a, grids_b, Ts, t=None, bx=0, by=0, kchunk=0):
+        n = len(grids_a)
+        if n != len(grids_b) or n != len(Ts) or n == 0:
+            raise ValueError("need equal, non-empty lists of a grids, b grids and sweep counts")
+        for a, b in zip(grids_a, grids_b):
+            _same(a, b)
+        self.a, self.b = list(grids_a), list(grids_b)
+        self.dtype = grids_a[0].dtype
+        if any(x.dtype != self.dtype for x in grids_a):
+            raise TypeError("all grids of a batch share one dtype")
+        lib = _lib.load()
+        code = dtype_code(grids_a[0])
+        G = (Grid * n)(*[grid_of(x) for x in grids_a])
+        T = (ctypes.c_int * n)(*[int(v) for v in Ts])
+        A = (ctypes.c_void_p * n)(*[x.data_ptr() for x in grids_a])
+        B = (ctypes.c_void_p * n)(*[x.data_ptr() for x in grids_b])
+        tile = _tile(t, bx, by, kchunk)
+        nbytes = lib.jacobi_batched_plan_bytes(code, n, G, T, ctypes.byref(tile))
+        if nbytes == 0:
+            check(_lib.JAC_EARG)
+        self._host = (ctypes.c_ubyte * nbytes)()
+        self.out_idx = (ctypes.c_int * n)()
+        check(lib.jacobi_batched_plan(code, n, G, A, B, T, ctypes.byref(tile), self._host, nbytes,
+                                      self.out_idx))
+        dev = grids_a[0].device
+        self.plan_dev = torch.frombuffer(bytearray(self._host), dtype=torch.uint8).to(dev)
+        ws = lib.jacobi_batched_workspace(self._host)
+        self.ws = torch.zeros(max(ws, 8), dtype=torch.uint8, device=dev)
+        self.device = dev
+
+    def run(self, mode="relaxed"):
+        with torch.cuda.device(self.device):
+            check(_lib.load().jacobi_batched_run(self._host, _ptr(self.plan_dev), _ptr(self.ws),
+                                                 self.ws.numel(), self.MODES[mode],
+                                                 _stream(self.plan_dev)))
+        return self
+
+    def results(self):
+        return [b if o else a for a, b, o in zip(self.a, self.b, self.out_idx)]
+
+    def wait_error(self):
+        """True if a relaxed-mode wait gave up (read after synchronising)."""
+        return bool(self.ws[-4:].view(torch.int32).item())
+
+
+def batched(grids_a, grids_b, Ts, t=None, bx=0, by=0, kchunk=0, mode="relaxed"):
+    """Level T[m] of every grid m (one launch); returns the result tensors."""
+    return BatchPlan(grids_a, grids_b, Ts, t, bx, by, kchunk).run(mode).results()

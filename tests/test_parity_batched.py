@@ -1,0 +1,93 @@
+"""GPU parity of the batched runs (persistent with per-block counters, and
+lockstep with one launch per pass) with the CPU oracle, and of their replay
+from a captured graph."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0912_4506_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def make_batch(shapes, seed=0, dtype=torch.float64):
+    us = [inputs.batch_grid(s, m, seed=seed) for m, s in enumerate(shapes)]
+    a = [torch.from_numpy(u).to("cuda", dtype) for u in us]
+    b = [torch.full_like(x, float("nan")) for x in a]
+    return us, a, b
+
+
+SHAPES = [(32, 32, 32), (45, 17, 80), (130, 70, 33), (7, 200, 19), (1, 1, 1), (96, 96, 96),
+          (61, 3, 129)]
+
+
+@pytest.mark.parametrize("mode", ["relaxed", "lockstep"])
+@pytest.mark.parametrize("t,tile", [(5, (64, 48)), (4, (128, 32)), (2, (64, 32)), (3, (64, 64))])
+def test_batched_bitwise(jac, mode, t, tile):
+    Ts = [50, 17, 23, 9, 4, 31, 12]
+    us, a, b = make_batch(SHAPES)
+    plan = jac.BatchPlan(a, b, Ts, t=t, bx=tile[0], by=tile[1])
+    plan.run(mode)
+    torch.cuda.synchronize()
+    assert not plan.wait_error()
+    for m, (u, T, out) in enumerate(zip(us, Ts, plan.results())):
+        assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T)), (m, mode, t, tile)
+
+
+def test_batched_small_kchunk(jac):
+    """Several k chunks per grid: dependencies between chunks of one pass."""
+    us, a, b = make_batch([(70, 50, 90), (33, 33, 40)])
+    plan = jac.BatchPlan(a, b, [20, 13], t=4, bx=64, by=48, kchunk=8)
+    plan.run("relaxed")
+    torch.cuda.synchronize()
+    for u, T, out in zip(us, [20, 13], plan.results()):
+        assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T))
+
+
+def test_graph_replay(jac):
+    """Capture the run once, replay it several times with eager work and
+    synchronisations between replays; every replay matches the eager run."""
+    us, a, b = make_batch(SHAPES[:4], seed=3)
+    Ts = [20, 10, 15, 5]
+    a0 = [x.clone() for x in a]
+    plan = jac.BatchPlan(a, b, Ts, t=5, bx=64, by=48)
+    plan.run("relaxed")
+    torch.cuda.synchronize()
+    eager = [x.clone() for x in plan.results()]
+    for m in range(4):
+        assert np.array_equal(eager[m].cpu().numpy(), oracle.sweeps(us[m], Ts[m]))
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for x, x0 in zip(a, a0):
+            x.copy_(x0)
+        plan.run("relaxed")  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.run("relaxed")
+    for rep in range(4):
+        for x, x0 in zip(a, a0):
+            x.copy_(x0)
+        for x in b:
+            x.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for m, out in enumerate(plan.results()):
+            assert torch.equal(out, eager[m]), (rep, m)
+
+
+def test_batch_config_64_grids(jac):
+    """The batched workload: 64 cubic grids, edges log-uniform in [32, 256],
+    T = 50, FP64, one persistent launch; every grid bitwise vs the oracle."""
+    edges = inputs.batch_edges(64, seed=0)
+    us, a, b = make_batch(edges, seed=0)
+    Ts = [50] * 64
+    plan = jac.BatchPlan(a, b, Ts, t=5, bx=64, by=48)
+    plan.run("relaxed")
+    torch.cuda.synchronize()
+    for m, (u, out) in enumerate(zip(us, plan.results())):
+        assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, 50)), m
