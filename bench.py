@@ -1,18 +1,24 @@
 """Benchmark: 512^3 FP64 Jacobi, T = 100 sweeps, temporally blocked vs plain.
 
-One step = T = 100 sweeps of the 512^3 (514^3 arrays) FP64 grid through
-jacobi_tblock at the blocking depth t being measured; inputs are resident in
-HBM before the timed region, and consecutive steps continue the iteration
-(level 100 of one step is level 0 of the next; the work does not depend on
-the values).  Prints ONE JSON line (rank 0, N = 1):
+Default workload (one JSON line): one step = T = 100 sweeps of the 512^3
+interior (514^3 arrays) FP64 grid through jacobi_tblock at the library's
+default blocking (--autotune: the autotuner's pick); inputs are resident in HBM before the timed region and
+consecutive steps continue the iteration (level 100 of one step is level 0
+of the next; the work does not depend on the values).
 
-  value     GLUP/s of the blocked run at the reported depth (512^3 * 100 / time)
-  roofline  the blocked kernel against HBM: algorithmic bytes per launch
-            (16 B per cell per pass: one read and one write of each cell) over
-            the kernel's average launch duration, measured with HIP events on
-            the stream the kernels run on, against the 8 TB/s HBM peak
-  plain     the plain sweep kernel under the same protocol
+  value         GLUP/s of the blocked run (512^3 * 100 / time per step)
+  roofline      the blocked kernel against HBM: algorithmic bytes per launch
+                (16 B per cell per pass, one read and one write of each cell)
+                over its average launch duration (HIP events on the stream the
+                kernels run on), against the 8 TB/s HBM peak; `traffic` is the
+                measured HBM traffic per launch when given with --traffic
+  plain         the plain one-pass-per-sweep kernel under the same protocol
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
+
+Other workloads (--workload): `batched` (64 grids, edges log-uniform in
+[32, 256], T = 50, one persistent launch), `adjoint` (256^3, T = 32, t = 8,
+forward + backward), `refine` (768^3 Laplace solve, FP32 inner / FP64 outer,
+vs all-FP64 Jacobi; runs many minutes).
 """
 import argparse
 import json
@@ -25,9 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-N = 512
-T = 100
 HBM_PEAK_GBS = 8000.0
+# (t, bx, by) -> measured HBM GB per launch of the blocked kernel at 512^3 FP64
+MEASURED_TRAFFIC_GB = {(4, 64, 48): 2.533}
+METRIC = "GLUP/s & % roofline, 512³ FP64 Jacobi T=100: temporal-blocked vs plain"
 
 
 def ensure_built():
@@ -37,8 +44,9 @@ def ensure_built():
         __graft_entry__.build()
 
 
-def time_steps(fn, steps, warmup, stream):
+def time_steps(fn, steps, warmup):
     import torch
+    stream = torch.cuda.current_stream()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -53,32 +61,254 @@ def time_steps(fn, steps, warmup, stream):
 
 
 def copy_bandwidth(jac, nbytes=2 << 30, reps=5):
-    """M_s: the library's copy kernel over two nbytes arrays (beyond the
-    256 MB last-level cache), bytes read + written per second."""
+    """M_s (Eq. 2): the library's copy kernel over two nbytes arrays (beyond
+    the 256 MB last-level cache); bytes read + written per second."""
     import torch
     src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
-    stream = torch.cuda.current_stream()
-    ms = time_steps(lambda: jac.copy(dst, src), reps, 2, stream)
+    ms = time_steps(lambda: jac.copy(dst, src), reps, 2)
     del src, dst
     torch.cuda.empty_cache()
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(u, target_s=12.0):
-    """The CPU oracle (as it stands) on the host cores: whole 512^3 grid for
-    as many sweeps as fit about target_s seconds."""
+def cpu_baseline(u, T, lups_per_sweep, target_s=12.0):
+    """The CPU oracle, as it stands, on the host cores: the whole grid for as
+    many of the T sweeps as fit about target_s seconds."""
     import oracle
     t0 = time.perf_counter()
+    oracle.sweeps(u, 2)
+    t1 = time.perf_counter()
     oracle.sweeps(u, 1)
-    t1 = time.perf_counter() - t0
-    sweeps = max(1, min(T, int(target_s / max(t1, 1e-3))))
+    t2 = time.perf_counter()
+    per_sweep = max((t1 - t0) - (t2 - t1), 1e-3)
+    sweeps = max(1, min(T, int(target_s / per_sweep)))
     t0 = time.perf_counter()
     oracle.sweeps(u, sweeps)
     dt = time.perf_counter() - t0
-    return {"value": round(N ** 3 * sweeps / dt / 1e9, 4), "unit": "GLUP/s",
+    n = round(u.shape[0] - 2)
+    return {"value": round(lups_per_sweep * sweeps / dt / 1e9, 4), "unit": "GLUP/s",
             "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{N}^3 FP64 grid, {sweeps} of the {T} sweeps, one run ({dt:.1f} s)"}
+            "sample": f"{n}^3 FP64 grid, {sweeps} of the {T} sweeps, one run ({dt:.1f} s)"}
+
+
+def bench_metric(args):
+    import torch
+    from paper_0912_4506_amd import inputs, jacobi as jac
+
+    N, T = 512, 100
+    u = inputs.grid(N, N, N, seed=0)
+    a = torch.from_numpy(u).to("cuda")
+    b = torch.empty_like(a)
+    lups = N ** 3 * T
+    cell_bytes = 16 * N ** 3  # one read + one write of each cell per pass
+
+    if args.autotune:
+        # the library's autotuner picks the blocking (every shape and depth)
+        (t, bx, by), _ = jac.autotune(a, b, T, tmax=args.tmax, reps=1)
+        a.copy_(torch.from_numpy(u))
+    else:
+        # the library's default blocking for this grid (or a pinned choice)
+        t = args.t or jac.default_tile(a.shape, T)[0]
+        bx, by = (args.bx, args.by) if args.bx else jac.default_tile(a.shape, T, t)[1:3]
+    state = {"a": a, "b": b}
+
+    def step(t=t, bx=bx, by=by):
+        out = jac.tblock(state["a"], state["b"], T, t=t, bx=bx, by=by)
+        if out is state["b"]:
+            state["a"], state["b"] = state["b"], state["a"]
+
+    ms = time_steps(step, args.steps, args.warmup)
+    passes = math.ceil(T / t)
+    kernel_ms = ms / passes
+    tile = jac.default_tile(a.shape, T, t)
+
+    by_depth = {}
+    if args.depths:
+        for d in [int(x) for x in args.depths.split(",") if x]:
+            best = None
+            for (sx, sy) in jac.tile_menu(torch.float64):
+                try:
+                    dms = time_steps(lambda: jac.tblock(state["a"], state["b"], T, t=d, bx=sx, by=sy),
+                                     1, 1)
+                except Exception:
+                    continue
+                if best is None or dms < best[0]:
+                    best = (dms, sx, sy)
+            if best:
+                by_depth[str(d)] = {"glups": round(lups / (best[0] * 1e-3) / 1e9, 1),
+                                    "tile": [best[1], best[2]]}
+
+    plain = None
+    if not args.no_plain:
+        def pstep():
+            out = jac.plain(state["a"], state["b"], T)
+            if out is state["b"]:
+                state["a"], state["b"] = state["b"], state["a"]
+        pms = time_steps(pstep, max(1, args.steps // 2), 1)
+        plain = {"glups": round(lups / (pms * 1e-3) / 1e9, 2), "ms_per_step": round(pms, 3),
+                 "kernel_ms": round(pms / T, 4),
+                 "achieved_gbs": round(cell_bytes / (pms / T * 1e-3) / 1e9, 1)}
+
+    del a, b, state
+    torch.cuda.empty_cache()
+    ms_copy = copy_bandwidth(jac)
+    achieved = cell_bytes / (kernel_ms * 1e-3) / 1e9
+    # HBM traffic per launch of the blocked kernel, from the rocprofv3 PMC runs
+    # summarised in profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales
+    # the 2 GiB copy kernel gives); only for the kernel those runs measured
+    traffic = MEASURED_TRAFFIC_GB.get((t, bx, by))
+    if args.traffic:
+        traffic = float(args.traffic)
+    line = {
+        "metric": METRIC,
+        "value": round(lups / (ms * 1e-3) / 1e9, 2),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: uniform [0,1) interior and shell, numpy default_rng(0)",
+        "config": {"workload": "jacobi3d 512^3 interior (514^3 arrays), FP64, T=100, Dirichlet shell",
+                   "t": t, "tile_bx_by": [bx, by], "kchunk": tile[3], "passes": passes},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "traffic_unit": "GB per launch",
+                     "algorithmic_bytes_per_launch": cell_bytes},
+        "plain": plain,
+        "by_depth": by_depth,
+        "copy_bandwidth_gbs": round(ms_copy, 1),
+        "p0_glups": round(ms_copy / 16, 1),
+        "vs_plain": round((lups / (ms * 1e-3) / 1e9) / plain["glups"], 3) if plain else None,
+        "vs_p0": round((lups / (ms * 1e-3) / 1e9) / (ms_copy / 16), 3),
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(u, T, N ** 3)
+    return line
+
+
+def bench_batched(args):
+    import numpy as np
+    import torch
+    from paper_0912_4506_amd import inputs, jacobi as jac
+
+    edges = inputs.batch_edges(64, seed=0, cubic=not args.noncubic)
+    us = [inputs.batch_grid(e, m, seed=0) for m, e in enumerate(edges)]
+    a = [torch.from_numpy(x).to("cuda") for x in us]
+    b = [torch.empty_like(x) for x in a]
+    T = 50
+    lups = sum(nx * ny * nz for nx, ny, nz in edges) * T
+    (t, bx, by), _ = jac.autotune_batch(a, b, [T] * 64, reps=1)
+    plan = jac.BatchPlan(a, b, [T] * 64, t=t, bx=bx, by=by)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run("relaxed")
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.run("relaxed")
+    ms = time_steps(g.replay, args.steps, args.warmup)
+    lms = time_steps(lambda: plan.run("lockstep"), args.steps, 1)
+    # per-grid plain calls, one after another
+    def seq_plain():
+        for x, y in zip(a, b):
+            jac.plain(x, y, T)
+    pms = time_steps(seq_plain, max(1, args.steps // 2), 1)
+    def seq_tb():
+        for x, y in zip(a, b):
+            jac.tblock(x, y, T, t=t, bx=bx, by=by)
+    tms = time_steps(seq_tb, max(1, args.steps // 2), 1)
+    return {"metric": "batched GLUP/s, 64 grids (edges log-uniform in [32,256]) FP64 T=50",
+            "value": round(lups / (ms * 1e-3) / 1e9, 2), "unit": "GLUP/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "64 cubic grids" if not args.noncubic else "64 non-cubic grids",
+                       "interior_cells": int(lups // T), "t": t, "tile_bx_by": [bx, by],
+                       "graph": True},
+            "lockstep_glups": round(lups / (lms * 1e-3) / 1e9, 2),
+            "sequential_plain_glups": round(lups / (pms * 1e-3) / 1e9, 2),
+            "sequential_tblock_glups": round(lups / (tms * 1e-3) / 1e9, 2)}
+
+
+def bench_adjoint(args):
+    import torch
+    from paper_0912_4506_amd import inputs, jacobi as jac
+    from paper_0912_4506_amd.autograd import JacobiT
+
+    from paper_0912_4506_amd.autograd import checkpoints
+
+    n, T, every = 256, 32, 8
+    out = {"metric": "autograd forward+backward, 256^3, T=32, checkpoints every 8 levels",
+           "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "results": {}}
+    for dt in (torch.float64, torch.float32):
+        u = torch.from_numpy(inputs.grid(n, n, n, seed=0)).to("cuda", dt)
+        w = torch.from_numpy(inputs.adjoint_weights(n, n, n, seed=0)).to("cuda", dt)
+
+        def fwd_bwd_ckpt():
+            x = u.detach().requires_grad_(True)
+            A = checkpoints(x, T, every)[-1]
+            (w * A * A).sum().backward()
+
+        def fwd_bwd():
+            x = u.detach().requires_grad_(True)
+            A = JacobiT.apply(x, T)
+            (w * A * A).sum().backward()
+
+        cms = time_steps(fwd_bwd_ckpt, args.steps, args.warmup)
+        ms = time_steps(fwd_bwd, args.steps, args.warmup)
+        a = u.clone()
+        b = torch.empty_like(a)
+        pms = time_steps(lambda: jac.plain(a, b, T), args.steps, 1)
+        out["results"]["f64" if dt == torch.float64 else "f32"] = {
+            "fwd_bwd_checkpointed_ms": round(cms, 3), "fwd_bwd_ms": round(ms, 3),
+            "plain_forward_ms": round(pms, 3),
+            "ratio_to_plain_forward": round(cms / pms, 3)}
+    out["value"] = out["results"]["f64"]["fwd_bwd_checkpointed_ms"]
+    return out
+
+
+def bench_refine(args):
+    import numpy as np
+    import torch
+    from paper_0912_4506_amd import inputs
+    from paper_0912_4506_amd.refine import refine_solve, jacobi_solve_f64
+
+    n = args.refine_n
+    g = inputs.laplace_problem(n, n, n, seed=0)
+    res = {}
+    x = torch.from_numpy(g).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, outer, rel = refine_solve(x, tol=1e-10, inner=50, t=8, check_every=args.check_every,
+                                 callback=lambda it, r: print(f"  mixed outer {it} rel {r:.3e}",
+                                                              file=sys.stderr, flush=True)
+                                 if it % 2000 == 0 else None)
+    torch.cuda.synchronize()
+    res["mixed"] = {"seconds": round(time.perf_counter() - t0, 2), "outer": outer,
+                    "sweeps": outer * 50, "rel_residual": rel}
+    del x
+    if not args.skip_f64:
+        x = torch.from_numpy(g).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, sweeps, rel = jacobi_solve_f64(x, tol=1e-10, check=50 * args.check_every, t=8,
+                                          callback=lambda s, r: print(f"  f64 sweeps {s} rel {r:.3e}",
+                                                                      file=sys.stderr, flush=True)
+                                          if s % 100000 == 0 else None)
+        torch.cuda.synchronize()
+        res["fp64_t8"] = {"seconds": round(time.perf_counter() - t0, 2), "sweeps": sweeps,
+                          "rel_residual": rel}
+    return {"metric": f"Laplace solve {n}^3 to 1e-10 relative residual", "unit": "s",
+            "value": res["mixed"]["seconds"], "higher_is_better": False, "n_gpus": 1,
+            "data": "synthetic: uniform [0,1) Dirichlet data, zero initial interior",
+            "results": res}
 
 
 def main():
@@ -86,92 +316,33 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--depths", default="1,2,4,5",
-                    help="blocking depths to measure; the best one is reported")
+    ap.add_argument("--workload", default="metric",
+                    choices=["metric", "batched", "adjoint", "refine"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner pick the blocking first")
+    ap.add_argument("--tmax", type=int, default=8, help="deepest blocking depth the autotuner tries")
+    ap.add_argument("--t", type=int, default=0, help="pin the blocking depth (skips autotuning)")
+    ap.add_argument("--bx", type=int, default=0, help="pin the block shape (with --t)")
+    ap.add_argument("--by", type=int, default=0)
+    ap.add_argument("--depths", default="1,2,3,4,5,6",
+                    help="depths reported in by_depth (best block shape each)")
+    ap.add_argument("--traffic", default=None,
+                    help="measured HBM GB per blocked launch to report as roofline.traffic")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--noncubic", action="store_true")
+    ap.add_argument("--refine-n", type=int, default=768)
+    ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--skip-f64", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); this build has no "
-              "multi-GPU path", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); there is no multi-GPU "
+              "path in this build", file=sys.stderr)
         sys.exit(2)
-
     ensure_built()
-    import numpy as np
-    import torch
-
-    from paper_0912_4506_amd import inputs, jacobi as jac
-
-    u = inputs.grid(N, N, N, seed=0)
-    a = torch.from_numpy(u).to("cuda")
-    b = torch.empty_like(a)
-    stream = torch.cuda.current_stream()
-    lups = N ** 3 * T
-    cell_bytes = 16 * N ** 3  # one read + one write of each cell per pass
-
-    results = {}
-    for t in [int(x) for x in args.depths.split(",") if x]:
-        state = {"a": a, "b": b}
-
-        def step(t=t, state=state):
-            out = jac.tblock(state["a"], state["b"], T, t=t)
-            if out is state["b"]:
-                state["a"], state["b"] = state["b"], state["a"]
-
-        ms = time_steps(step, args.steps, args.warmup, stream)
-        passes = math.ceil(T / t)
-        tile = jac.default_tile(a.shape, T, t)
-        results[t] = {"ms_per_step": ms, "glups": lups / (ms * 1e-3) / 1e9, "passes": passes,
-                      "kernel_ms": ms / passes, "tile": tile}
-    best_t = max(results, key=lambda t: results[t]["glups"])
-    best = results[best_t]
-
-    plain = None
-    if not args.no_plain:
-        state = {"a": a, "b": b}
-
-        def pstep(state=state):
-            out = jac.plain(state["a"], state["b"], T)
-            if out is state["b"]:
-                state["a"], state["b"] = state["b"], state["a"]
-
-        pms = time_steps(pstep, max(1, args.steps // 2), 1, stream)
-        plain = {"glups": round(lups / (pms * 1e-3) / 1e9, 2), "ms_per_step": round(pms, 3),
-                 "kernel_ms": round(pms / T, 4),
-                 "hbm_gbs": round(cell_bytes / (pms / T * 1e-3) / 1e9, 1)}
-
-    del a, b
-    torch.cuda.empty_cache()
-    ms_copy = copy_bandwidth(jac)
-
-    achieved = cell_bytes / (best["kernel_ms"] * 1e-3) / 1e9
-    line = {
-        "metric": "GLUP/s & % roofline, 512³ FP64 Jacobi T=100: temporal-blocked vs plain",
-        "value": round(best["glups"], 2),
-        "unit": "GLUP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(best["ms_per_step"], 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic: uniform [0,1) grid from numpy default_rng(0), interior and shell",
-        "config": {"workload": f"jacobi3d {N}^3 interior (514^3 arrays) FP64, T={T}, Dirichlet shell",
-                   "t": best_t, "tile_bx_by": best["tile"][1:3], "kchunk": best["tile"][3],
-                   "passes": best["passes"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
-        "plain": plain,
-        "by_depth": {str(t): {"glups": round(r["glups"], 2), "kernel_ms": round(r["kernel_ms"], 4)}
-                     for t, r in sorted(results.items())},
-        "copy_bandwidth_gbs": round(ms_copy, 1),
-        "roofline_p0_glups": round(ms_copy / 16, 2),
-    }
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(u)
-    print(json.dumps(line), flush=True)
+    fn = {"metric": bench_metric, "batched": bench_batched, "adjoint": bench_adjoint,
+          "refine": bench_refine}[args.workload]
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -194,6 +194,19 @@ int jacobi_fill(int dtype, const jac_grid_t *g, void *x, double value,
  * both pointers 16-byte aligned; the ranges must not overlap. */
 int jacobi_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/* Autotuner (the paper finds its blocking parameters experimentally,
+ * Sect. 1.5): times jacobi_tblock for T sweeps on the caller's grids a and b
+ * (whose contents it overwrites) for every menu block shape and depth
+ * t = 1..tmax (0 = JAC_MAX_DEPTH) that fits the grid and compiles without
+ * register spills, `reps` timed runs each after one warm-up, on `stream`
+ * (synchronising it).  Writes the fastest choice to *best_host (kchunk = 0,
+ * library choice) and its time per run in ms to *best_ms_host (may be NULL),
+ * and remembers it for the process: later jacobi_tblock calls on the same
+ * dtype, geometry and T with t, bx, by all 0 use it. */
+int jacobi_autotune(int dtype, const jac_grid_t *g, void *a, void *b, int T,
+                    int tmax, int reps, jac_tile_t *best_host,
+                    float *best_ms_host, void *stream);
+
 /* Supported (bx, by) pairs for jacobi_tblock / jacobi_adjoint: writes up to
  * `cap` pairs into pairs_host[2*n], [2*n+1] and returns the number available. */
 int jacobi_tile_menu(int dtype, int *pairs_host, int cap);

@@ -11,8 +11,10 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 
 #include "jacobi.h"
 #include "kernels.h"
@@ -208,12 +210,63 @@ void plan_k(const Geo &g, int slots, TbPlan *p, int kchunk_req)
     p->nkc = (int)((g.nz + p->kchunk - 1) / p->kchunk);
 }
 
-int default_depth(int dtype) { return dtype == JAC_F64 ? 4 : 6; }
+// ---------------------------------------------------------- tuning cache --
+// Choices made by jacobi_autotune, per (dtype, geometry, T), for the process.
+using TuneKey = std::tuple<int, int64_t, int64_t, int64_t, int64_t, int64_t, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, jac_tile_t> g_tune;
 
-const jac::TileShape &default_shape(int dtype, int t)
+bool tuned(int dtype, const Geo &g, int T, jac_tile_t *out)
 {
-    (void)dtype;
-    (void)t;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(TuneKey{dtype, g.nx, g.ny, g.nz, g.sy, g.sz, T});
+    if (it == g_tune.end())
+        return false;
+    *out = it->second;
+    return true;
+}
+
+// What a blocking choice is for: the kind of kernel it selects.
+enum { KIND_PLAIN = 0, KIND_RHS = 1, KIND_TRACE = 2, KIND_BATCH = 3 };
+
+// Untuned default depth, from 512^3 (single grid) and 64-grid batch runs on
+// MI355X.
+int default_depth(int dtype, int kind)
+{
+    if (dtype == JAC_F64)
+        return kind == KIND_BATCH ? 5 : 4;
+    return 6;
+}
+
+// Per-lane scratch bytes (register spills) of the kernel a choice selects;
+// -1 when unknown (no device visible).
+int kind_scratch(int dtype, int kind, int cfg, int depth)
+{
+    if (kind == KIND_BATCH)
+        return jac::batched_scratch(dtype, cfg, depth);
+    const int mode = kind == KIND_RHS ? jac::MODE_RHS : kind == KIND_TRACE ? jac::MODE_TRACE
+                                                                          : jac::MODE_PLAIN;
+    return jac::tblock_scratch(dtype, cfg, depth, mode);
+}
+
+// Untuned default block shape: the first of a preference order (measured on
+// 512^3 FP64 runs) that has valid cells at depth t and compiles without
+// register spills for this kind of kernel.
+const jac::TileShape &default_shape(int dtype, int kind, int t)
+{
+    static const int pref[][2] = {{64, 48}, {64, 64}, {128, 32}, {64, 32}, {128, 24}, {128, 16}};
+    for (const auto &p : pref) {
+        const jac::TileShape *s = find_shape(p[0], p[1]);
+        if (!s)
+            continue;
+        const int hi = (s->ci % 2 == 0) ? even_up(t) : t;
+        const int need = kind == KIND_BATCH ? 3 : 2;  // batches need valid width >= halo
+        if (s->bx() - need * hi < (kind == KIND_BATCH ? 0 : 1) || s->by() - need * t < (kind == KIND_BATCH ? 0 : 1))
+            continue;
+        if (kind_scratch(dtype, kind, s->id, t) > 0)
+            continue;
+        return *s;
+    }
     return kMenu[0];
 }
 
@@ -221,12 +274,21 @@ const jac::TileShape &default_shape(int dtype, int t)
 size_t shape_lds(int dtype, const jac::TileShape &s, int t)
 {
     const size_t one = (size_t)s.waves * 2 * t * s.ci * 64 * elem_size(dtype);
-    return 2 * one <= 160 * 1024 ? 2 * one : one;  // double-buffered when it fits
+    return 2 * one <= 159 * 1024 ? 2 * one : one;  // double-buffered when it fits
 }
 
-int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out)
+int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out, const Geo *geo = nullptr,
+                 int kind = KIND_PLAIN)
 {
     jac_tile_t r = tile ? *tile : jac_tile_t{0, 0, 0, 0};
+    jac_tile_t c;
+    if (geo && r.t == 0 && r.bx == 0 && r.by == 0 && tuned(dtype, *geo, T, &c)) {
+        if (r.kchunk == 0)
+            r.kchunk = c.kchunk;
+        r.t = c.t;
+        r.bx = c.bx;
+        r.by = c.by;
+    }
     if (r.t < 0 || r.t > JAC_MAX_DEPTH)
         return fail(JAC_EARG, "blocking depth t = %d outside 0..%d", r.t, JAC_MAX_DEPTH);
     if (r.kchunk < 0)
@@ -237,11 +299,11 @@ int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out)
         return fail(JAC_EUNSUPPORTED, "no kernel for block shape %d x %d (see jacobi_tile_menu)",
                     r.bx, r.by);
     if (r.t == 0)
-        r.t = default_depth(dtype);
+        r.t = default_depth(dtype, kind);
     if (T > 0 && r.t > T)
         r.t = T;
     if (r.bx == 0) {
-        const jac::TileShape &s = default_shape(dtype, r.t);
+        const jac::TileShape &s = default_shape(dtype, kind, r.t);
         r.bx = s.bx();
         r.by = s.by();
     }
@@ -281,7 +343,7 @@ int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, in
         if (!plan_ij(g, *shape, depth, &plan))
             return fail(JAC_EUNSUPPORTED, "block %d x %d has no valid cells at depth %d", tile.bx,
                         tile.by, depth);
-        if (shape_lds(dtype, *shape, depth) > dev.lds_per_block)
+        if (shape_lds(dtype, *shape, depth) + 1024 > dev.lds_per_block)
             return fail(JAC_EUNSUPPORTED, "block %d x %d at depth %d needs more LDS than the device has",
                         tile.bx, tile.by, depth);
         int occ = jac::tblock_occupancy(dtype, shape->id, depth, mode);
@@ -480,7 +542,7 @@ int jacobi_tblock(int dtype, const jac_grid_t *g, void *a, void *b, int T, const
             return fail(JAC_EARG, "rhs overlaps a or b");
     }
     jac_tile_t tl;
-    if ((rc = resolve_tile(dtype, tile, T, &tl)))
+    if ((rc = resolve_tile(dtype, tile, T, &tl, rhs ? nullptr : &geo, rhs ? KIND_RHS : KIND_PLAIN)))
         return rc;
     *out_idx = 0;
     if (T == 0)
@@ -528,7 +590,7 @@ int jacobi_adjoint(int dtype, const jac_grid_t *g, void *lam_a, void *lam_b, int
     if (!out_idx)
         return fail(JAC_EARG, "out_idx is NULL");
     jac_tile_t tl;
-    if ((rc = resolve_tile(dtype, tile, T, &tl)))
+    if ((rc = resolve_tile(dtype, tile, T, &tl, nullptr, KIND_TRACE)))
         return rc;
     *out_idx = 0;
     if (T == 0)
@@ -632,7 +694,7 @@ static int batch_common(int dtype, int n, const jac_grid_t *g, const int *T, con
     int Tmax = 0;
     for (int m = 0; m < n; ++m)
         Tmax = std::max(Tmax, T[m]);
-    if ((rc = resolve_tile(dtype, tile, Tmax, tl)))
+    if ((rc = resolve_tile(dtype, tile, Tmax, tl, nullptr, KIND_BATCH)))
         return rc;
     if (tl->t < 1)
         tl->t = 1;
@@ -850,6 +912,84 @@ int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws, si
     return JAC_OK;
 }
 
+int jacobi_autotune(int dtype, const jac_grid_t *g, void *a, void *b, int T, int tmax, int reps,
+                    jac_tile_t *best_host, float *best_ms_host, void *stream)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_grid(g, &geo)) ||
+        (rc = check_pair(dtype, geo, a, b)))
+        return rc;
+    if (T < 1)
+        return fail(JAC_EARG, "T = %d: autotuning needs T >= 1", T);
+    if (tmax < 0 || tmax > JAC_MAX_DEPTH)
+        return fail(JAC_EARG, "tmax = %d outside 0..%d", tmax, JAC_MAX_DEPTH);
+    if (!best_host)
+        return fail(JAC_EARG, "best_host is NULL");
+    if (tmax == 0)
+        tmax = JAC_MAX_DEPTH;
+    if (reps < 1)
+        reps = 2;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess)
+        return hip_fail(e, "autotune event");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(e, "autotune event");
+    }
+    const DeviceFacts dev = device_facts();
+    float best = 1e30f;
+    jac_tile_t pick{0, 0, 0, 0};
+    int out = 0;
+    for (int n = 0; n < kMenuN; ++n)
+        for (int t = 1; t <= std::min(tmax, T); ++t) {
+            const jac::TileShape &s = kMenu[n];
+            TbPlan probe;
+            if (!plan_ij(geo, s, t, &probe) || shape_lds(dtype, s, t) + 1024 > dev.lds_per_block)
+                continue;
+            // the deepest pass of the split; kernels that spill are skipped
+            const int P = (T + t - 1) / t, dmax = T / P + (T % P ? 1 : 0);
+            if (jac::tblock_scratch(dtype, s.id, dmax, jac::MODE_PLAIN) != 0)
+                continue;
+            jac_tile_t cand{t, s.bx(), s.by(), 0};
+            if ((rc = jacobi_tblock(dtype, g, a, b, T, &cand, nullptr, stream, &out)))
+                break;  // warm-up; an error ends the search
+            hipEventRecord(e0, st);
+            for (int r = 0; r < reps && !rc; ++r)
+                rc = jacobi_tblock(dtype, g, a, b, T, &cand, nullptr, stream, &out);
+            hipEventRecord(e1, st);
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+                rc = hip_fail(e, "autotune timing");
+                break;
+            }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            ms /= reps;
+            if (!rc && ms < best) {
+                best = ms;
+                pick = cand;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc)
+        return rc;
+    if (pick.t == 0)
+        return fail(JAC_EUNSUPPORTED, "no candidate fits this grid");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[TuneKey{dtype, geo.nx, geo.ny, geo.nz, geo.sy, geo.sz, T}] = pick;
+    }
+    *best_host = pick;
+    if (best_ms_host)
+        *best_ms_host = best;
+    g_err.clear();
+    return JAC_OK;
+}
+
 int jacobi_copy(void *dst, const void *src, size_t bytes, void *stream)
 {
     g_err.clear();
@@ -891,7 +1031,7 @@ int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, jac_tile_t
     if (T < 0)
         return fail(JAC_EARG, "T = %d is negative", T);
     jac_tile_t req{t, 0, 0, 0};
-    if ((rc = resolve_tile(dtype, &req, T, tile_host)))
+    if ((rc = resolve_tile(dtype, &req, T, tile_host, &geo)))
         return rc;
     return JAC_OK;
 }

@@ -139,6 +139,10 @@ hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStre
 hipError_t launch_batched(int dtype, int cfg, int depth, const BatchLaunch &L, int nblocks,
                           hipStream_t st);
 int batched_occupancy(int dtype, int cfg, int depth);
+int batched_scratch(int dtype, int cfg, int depth);
+
+// Per-lane scratch (register spill) bytes of a tblock instance, -1 if none.
+int tblock_scratch(int dtype, int cfg, int depth, int mode);
 
 // Resident workgroups per CU of a tblock instance (0 when it cannot launch).
 int tblock_occupancy(int dtype, int cfg, int depth, int mode);

@@ -50,11 +50,12 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
 }
 
 // The exchange buffer is double-buffered (one barrier per stream step) when
-// two copies fit in the 160 KiB of LDS a gfx950 workgroup may use.
+// two copies fit in the 160 KiB of LDS a gfx950 workgroup may use, less 1 KiB
+// kept for the kernels' static LDS.
 template <typename real, int TL, int CI, int W>
 constexpr bool xch_double()
 {
-    return 2 * (W * 2 * TL * CI * 64) * sizeof(real) <= 160 * 1024;
+    return 2 * (W * 2 * TL * CI * 64) * sizeof(real) <= 159 * 1024;
 }
 
 template <typename real, int TL, int CI, int W>

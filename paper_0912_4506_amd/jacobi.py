@@ -233,3 +233,44 @@ class BatchPlan:
 def batched(grids_a, grids_b, Ts, t=None, bx=0, by=0, kchunk=0, mode="relaxed"):
     """Level T[m] of every grid m (one launch); returns the result tensors."""
     return BatchPlan(grids_a, grids_b, Ts, t, bx, by, kchunk).run(mode).results()
+
+
+def autotune(a, b, T, tmax=0, reps=2):
+    """Time every block shape and depth for T sweeps on grids a, b (their
+    contents are overwritten); returns ((t, bx, by), ms) of the fastest and
+    makes it the library's choice for this geometry and T."""
+    _same(a, b)
+    best = Tile()
+    ms = ctypes.c_float(0)
+    with torch.cuda.device(a.device):
+        check(_lib.load().jacobi_autotune(dtype_code(a), ctypes.byref(grid_of(a)), _ptr(a), _ptr(b),
+                                          int(T), int(tmax), int(reps), ctypes.byref(best),
+                                          ctypes.byref(ms), _stream(a)))
+    return (best.t, best.bx, best.by), ms.value
+
+
+def autotune_batch(grids_a, grids_b, Ts, candidates=None, mode="relaxed", reps=2):
+    """Pick the (t, bx, by) of a batched run by timing the whole batch for
+    each candidate (the grids' contents are overwritten).  Returns
+    ((t, bx, by), ms)."""
+    if candidates is None:
+        candidates = [(t, bx, by) for (bx, by) in tile_menu(grids_a[0].dtype) for t in range(2, 7)]
+    best, best_ms = None, float("inf")
+    st = torch.cuda.current_stream(grids_a[0].device)
+    for (t, bx, by) in candidates:
+        try:
+            plan = BatchPlan(grids_a, grids_b, Ts, t=t, bx=bx, by=by)
+            plan.run(mode)
+        except _lib.JacobiError:
+            continue
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            plan.run(mode)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if ms < best_ms:
+            best, best_ms = (t, bx, by), ms
+    return best, best_ms

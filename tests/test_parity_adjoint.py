@@ -98,6 +98,10 @@ def test_checkpoints_gradients(jac):
     ut = dev(u).requires_grad_(True)
     levels = checkpoints(ut, T, t)
     assert len(levels) == 3
+    # the same checkpoints with a different kernel depth give the same forward levels
+    lv2 = checkpoints(dev(u), T, t, depth=2)
+    for x, y in zip(levels, lv2):
+        assert torch.equal(x.detach(), y)
     w = [dev(inputs.adjoint_weights(nx, ny, nz, seed=s)) for s in range(3)]
     L = sum((wi * lv).sum() for wi, lv in zip(w, levels))
     L.backward()

@@ -151,3 +151,18 @@ def test_fp64_division_bitwise(jac):
     u[1:-1, 1, 0] = s            # i-1 face of cell (1, 1, k); every other neighbour 0
     got = run(jac, u, 1, t=1)
     assert np.array_equal(got[1:-1, 1, 1], s / 6.0)
+
+
+def test_autotune_choice_is_used_and_exact(jac):
+    """The autotuner returns a supported choice, the library then uses it for
+    that geometry, and results stay bitwise."""
+    nx, ny, nz, T = 90, 70, 60, 12
+    u = inputs.grid(nx, ny, nz, seed=2)
+    a = dev(u)
+    b = torch.empty_like(a)
+    (t, bx, by), ms = jac.autotune(a, b, T, tmax=6, reps=1)
+    assert 1 <= t <= 6 and (bx, by) in jac.tile_menu(torch.float64) and ms > 0
+    assert jac.default_tile(a.shape, T)[:3] == (t, bx, by)
+    a = dev(u)
+    out = jac.tblock(a, torch.empty_like(a), T)
+    assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T))
