@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # (t, bx, by) -> measured HBM GB per launch of the blocked kernel at 512^3 FP64
-MEASURED_TRAFFIC_GB = {(4, 64, 48): 2.533}
+MEASURED_TRAFFIC_GB = {(4, 64, 48, 8): 2.533}
 METRIC = "GLUP/s & % roofline, 512³ FP64 Jacobi T=100: temporal-blocked vs plain"
 
 
@@ -105,16 +105,17 @@ def bench_metric(args):
 
     if args.autotune:
         # the library's autotuner picks the blocking (every shape and depth)
-        (t, bx, by), _ = jac.autotune(a, b, T, tmax=args.tmax, reps=1)
+        (t, bx, by, w), _ = jac.autotune(a, b, T, tmax=args.tmax, reps=1)
         a.copy_(torch.from_numpy(u))
     else:
         # the library's default blocking for this grid (or a pinned choice)
         t = args.t or jac.default_tile(a.shape, T)[0]
-        bx, by = (args.bx, args.by) if args.bx else jac.default_tile(a.shape, T, t)[1:3]
+        d = jac.default_tile(a.shape, T, t)
+        bx, by, w = (args.bx, args.by, args.waves) if args.bx else (d[1], d[2], d[4])
     state = {"a": a, "b": b}
 
-    def step(t=t, bx=bx, by=by):
-        out = jac.tblock(state["a"], state["b"], T, t=t, bx=bx, by=by)
+    def step(t=t, bx=bx, by=by, w=w):
+        out = jac.tblock(state["a"], state["b"], T, t=t, bx=bx, by=by, waves=w)
         if out is state["b"]:
             state["a"], state["b"] = state["b"], state["a"]
 
@@ -127,17 +128,17 @@ def bench_metric(args):
     if args.depths:
         for d in [int(x) for x in args.depths.split(",") if x]:
             best = None
-            for (sx, sy) in jac.tile_menu(torch.float64):
+            for (sx, sy, sw) in jac.tile_menu(torch.float64):
                 try:
-                    dms = time_steps(lambda: jac.tblock(state["a"], state["b"], T, t=d, bx=sx, by=sy),
-                                     1, 1)
+                    dms = time_steps(lambda: jac.tblock(state["a"], state["b"], T, t=d, bx=sx, by=sy,
+                                                        waves=sw), 1, 1)
                 except Exception:
                     continue
                 if best is None or dms < best[0]:
-                    best = (dms, sx, sy)
+                    best = (dms, sx, sy, sw)
             if best:
                 by_depth[str(d)] = {"glups": round(lups / (best[0] * 1e-3) / 1e9, 1),
-                                    "tile": [best[1], best[2]]}
+                                    "tile": [best[1], best[2]], "waves": best[3]}
 
     plain = None
     if not args.no_plain:
@@ -157,7 +158,7 @@ def bench_metric(args):
     # HBM traffic per launch of the blocked kernel, from the rocprofv3 PMC runs
     # summarised in profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales
     # the 2 GiB copy kernel gives); only for the kernel those runs measured
-    traffic = MEASURED_TRAFFIC_GB.get((t, bx, by))
+    traffic = MEASURED_TRAFFIC_GB.get((t, bx, by, w))
     if args.traffic:
         traffic = float(args.traffic)
     line = {
@@ -174,7 +175,8 @@ def bench_metric(args):
         "dtype": "f64",
         "data": "synthetic: uniform [0,1) interior and shell, numpy default_rng(0)",
         "config": {"workload": "jacobi3d 512^3 interior (514^3 arrays), FP64, T=100, Dirichlet shell",
-                   "t": t, "tile_bx_by": [bx, by], "kchunk": tile[3], "passes": passes},
+                   "t": t, "tile_bx_by": [bx, by], "waves": w, "kchunk": tile[3],
+                   "passes": passes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_unit": "GB per launch",
@@ -202,8 +204,8 @@ def bench_batched(args):
     b = [torch.empty_like(x) for x in a]
     T = 50
     lups = sum(nx * ny * nz for nx, ny, nz in edges) * T
-    (t, bx, by), _ = jac.autotune_batch(a, b, [T] * 64, reps=1)
-    plan = jac.BatchPlan(a, b, [T] * 64, t=t, bx=bx, by=by)
+    (t, bx, by, w), _ = jac.autotune_batch(a, b, [T] * 64, reps=1)
+    plan = jac.BatchPlan(a, b, [T] * 64, t=t, bx=bx, by=by, waves=w)
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -222,14 +224,14 @@ def bench_batched(args):
     pms = time_steps(seq_plain, max(1, args.steps // 2), 1)
     def seq_tb():
         for x, y in zip(a, b):
-            jac.tblock(x, y, T, t=t, bx=bx, by=by)
+            jac.tblock(x, y, T, t=t, bx=bx, by=by, waves=w)
     tms = time_steps(seq_tb, max(1, args.steps // 2), 1)
     return {"metric": "batched GLUP/s, 64 grids (edges log-uniform in [32,256]) FP64 T=50",
             "value": round(lups / (ms * 1e-3) / 1e9, 2), "unit": "GLUP/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
             "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "64 cubic grids" if not args.noncubic else "64 non-cubic grids",
-                       "interior_cells": int(lups // T), "t": t, "tile_bx_by": [bx, by],
+                       "interior_cells": int(lups // T), "t": t, "tile_bx_by": [bx, by], "waves": w,
                        "graph": True},
             "lockstep_glups": round(lups / (lms * 1e-3) / 1e9, 2),
             "sequential_plain_glups": round(lups / (pms * 1e-3) / 1e9, 2),
@@ -324,6 +326,7 @@ def main():
     ap.add_argument("--t", type=int, default=0, help="pin the blocking depth (skips autotuning)")
     ap.add_argument("--bx", type=int, default=0, help="pin the block shape (with --t)")
     ap.add_argument("--by", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--depths", default="1,2,3,4,5,6",
                     help="depths reported in by_depth (best block shape each)")
     ap.add_argument("--traffic", default=None,

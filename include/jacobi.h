@@ -71,9 +71,12 @@ typedef struct jac_grid {
  *          cell per side and level, Sect. 2.1).  Supported pairs are listed by
  *          jacobi_tile_menu(); 0 = library choice.
  *   kchunk planes of output per workgroup along k (the k range is split so
- *          that the chip has enough workgroups); 0 = library choice. */
+ *          that the chip has enough workgroups); 0 = library choice.
+ *   waves  64-lane wavefronts per workgroup for the block (several kernels
+ *          may cover one bx x by, e.g. 8 waves of 6 rows or 16 waves of 3);
+ *          0 = library choice. */
 typedef struct jac_tile {
-    int32_t t, bx, by, kchunk;
+    int32_t t, bx, by, kchunk, waves;
 } jac_tile_t;
 
 #define JAC_MAX_DEPTH 8
@@ -207,9 +210,10 @@ int jacobi_autotune(int dtype, const jac_grid_t *g, void *a, void *b, int T,
                     int tmax, int reps, jac_tile_t *best_host,
                     float *best_ms_host, void *stream);
 
-/* Supported (bx, by) pairs for jacobi_tblock / jacobi_adjoint: writes up to
- * `cap` pairs into pairs_host[2*n], [2*n+1] and returns the number available. */
-int jacobi_tile_menu(int dtype, int *pairs_host, int cap);
+/* Supported block shapes for jacobi_tblock / jacobi_adjoint / batches: writes
+ * up to `cap` triples (bx, by, waves) into shapes_host[3*n .. 3*n+2] and
+ * returns the number available. */
+int jacobi_tile_menu(int dtype, int *shapes_host, int cap);
 
 /* The tile jacobi_tblock uses for (dtype, g, T, t) when tile fields are 0
  * (t = 0: library choice of t as well).  Writes *tile_host; returns JAC_OK. */

@@ -25,7 +25,7 @@ class Grid(ctypes.Structure):
 
 class Tile(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int32), ("bx", ctypes.c_int32), ("by", ctypes.c_int32),
-                ("kchunk", ctypes.c_int32)]
+                ("kchunk", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
 class JacobiError(RuntimeError):

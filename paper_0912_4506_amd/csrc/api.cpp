@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -128,6 +129,16 @@ DeviceFacts device_facts()
     return f;
 }
 
+// JACOBI_DEBUG=1 in the environment prints every pass plan to stderr.
+bool debug_plans()
+{
+    static const bool on = [] {
+        const char *v = getenv("JACOBI_DEBUG");
+        return v && *v && *v != '0';
+    }();
+    return on;
+}
+
 // --------------------------------------------------------------- tile menu --
 const jac::TileShape kMenu[] = {
 #define JAC_ROW(ID, CI, R, W) jac::TileShape{ID, CI, R, W},
@@ -136,10 +147,12 @@ const jac::TileShape kMenu[] = {
 };
 const int kMenuN = (int)(sizeof kMenu / sizeof kMenu[0]);
 
-const jac::TileShape *find_shape(int bx, int by)
+// The menu entry of block shape bx x by with `waves` waves per workgroup
+// (0: the first such entry).
+const jac::TileShape *find_shape(int bx, int by, int waves = 0)
 {
     for (int n = 0; n < kMenuN; ++n)
-        if (kMenu[n].bx() == bx && kMenu[n].by() == by)
+        if (kMenu[n].bx() == bx && kMenu[n].by() == by && (waves == 0 || kMenu[n].waves == waves))
             return &kMenu[n];
     return nullptr;
 }
@@ -147,11 +160,13 @@ const jac::TileShape *find_shape(int bx, int by)
 int even_up(int v) { return (v + 1) & ~1; }
 
 // Geometry of one temporally blocked pass at depth t with block shape s.
+// (For a single-grid pass nkc is the number of workgroups and kchunk their
+// share of planes; for a batch grid they are the k chunks of its blocks.)
 struct TbPlan {
     const jac::TileShape *shape;
     int t;
     int hi, nti, ntj, nkc, kchunk;
-    int64_t blocks() const { return (int64_t)nti * ntj * nkc; }
+    int64_t blocks() const { return nkc; }
 };
 
 // Blocks along one axis of n interior cells for blocks w wide with halo h:
@@ -182,32 +197,35 @@ bool plan_ij(const Geo &g, const jac::TileShape &s, int t, TbPlan *p)
 }
 
 // Split k so that the blocks fill the chip: minimise the modelled time
-// ceil(blocks / slots) * (kchunk + 2t), the number of rounds times the
-// stream length of one block.
+// ceil(blocks / slots) * (kchunk + 2t + c0), the number of rounds times the
+// stream length of one block (a chunk streams 2t planes more than it writes)
+// plus a fixed start-up cost c0 of about 12 stream steps per block (measured
+// on 512^3 FP64 runs: one round of 256-plane chunks beats four rounds of
+// 57-plane chunks that the model without c0 prefers by 2%).
 void plan_k(const Geo &g, int slots, TbPlan *p, int kchunk_req)
 {
+    const int64_t nij = (int64_t)p->nti * p->ntj;
     if (kchunk_req > 0) {
         p->kchunk = (int)std::min<int64_t>(kchunk_req, g.nz);
-        p->nkc = (int)((g.nz + p->kchunk - 1) / p->kchunk);
-        return;
-    }
-    const int64_t nij = (int64_t)p->nti * p->ntj;
-    double best = 1e300;
-    int best_n = 1;
-    const int64_t nmax = std::min<int64_t>(g.nz, 4096);
-    for (int64_t n = 1; n <= nmax; ++n) {
-        const int64_t kc = (g.nz + n - 1) / n;
-        if ((g.nz + kc - 1) / kc != n)
-            continue;  // same chunking as a smaller n
-        const int64_t rounds = (nij * n + slots - 1) / slots;
-        const double cost = (double)rounds * (double)(kc + 2 * p->t);
-        if (cost < best * (1 - 1e-9)) {
-            best = cost;
-            best_n = (int)n;
+    } else {
+        double best = 1e300;
+        int64_t best_kc = g.nz;
+        const int64_t nmax = std::min<int64_t>(g.nz, 4096);
+        for (int64_t n = 1; n <= nmax; ++n) {
+            const int64_t kc = (g.nz + n - 1) / n;
+            if ((g.nz + kc - 1) / kc != n)
+                continue;  // same chunking as a smaller n
+            const int64_t rounds = (nij * n + slots - 1) / slots;
+            const double cost = (double)rounds * (double)(kc + 2 * p->t + 12);
+            if (cost < best * (1 - 1e-9)) {
+                best = cost;
+                best_kc = kc;
+            }
         }
+        p->kchunk = (int)best_kc;
     }
-    p->kchunk = (int)((g.nz + best_n - 1) / best_n);
-    p->nkc = (int)((g.nz + p->kchunk - 1) / p->kchunk);
+    const int64_t nkc = (g.nz + p->kchunk - 1) / p->kchunk;
+    p->nkc = (int)std::min<int64_t>(nij * nkc, INT_MAX);  // workgroups of the launch
 }
 
 // ---------------------------------------------------------- tuning cache --
@@ -254,9 +272,11 @@ int kind_scratch(int dtype, int kind, int cfg, int depth)
 // register spills for this kind of kernel.
 const jac::TileShape &default_shape(int dtype, int kind, int t)
 {
-    static const int pref[][2] = {{64, 48}, {64, 64}, {128, 32}, {64, 32}, {128, 24}, {128, 16}};
+    static const int pref[][3] = {{64, 56, 8},   {64, 48, 8},  {64, 48, 16}, {64, 64, 8},
+                                  {64, 64, 16},  {128, 32, 8}, {128, 32, 16}, {64, 32, 8},
+                                  {128, 24, 8},  {128, 16, 8}};
     for (const auto &p : pref) {
-        const jac::TileShape *s = find_shape(p[0], p[1]);
+        const jac::TileShape *s = find_shape(p[0], p[1], p[2]);
         if (!s)
             continue;
         const int hi = (s->ci % 2 == 0) ? even_up(t) : t;
@@ -280,7 +300,7 @@ size_t shape_lds(int dtype, const jac::TileShape &s, int t)
 int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out, const Geo *geo = nullptr,
                  int kind = KIND_PLAIN)
 {
-    jac_tile_t r = tile ? *tile : jac_tile_t{0, 0, 0, 0};
+    jac_tile_t r = tile ? *tile : jac_tile_t{0, 0, 0, 0, 0};
     jac_tile_t c;
     if (geo && r.t == 0 && r.bx == 0 && r.by == 0 && tuned(dtype, *geo, T, &c)) {
         if (r.kchunk == 0)
@@ -288,6 +308,7 @@ int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out, cons
         r.t = c.t;
         r.bx = c.bx;
         r.by = c.by;
+        r.waves = c.waves;
     }
     if (r.t < 0 || r.t > JAC_MAX_DEPTH)
         return fail(JAC_EARG, "blocking depth t = %d outside 0..%d", r.t, JAC_MAX_DEPTH);
@@ -295,9 +316,12 @@ int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out, cons
         return fail(JAC_EARG, "kchunk = %d is negative", r.kchunk);
     if ((r.bx == 0) != (r.by == 0))
         return fail(JAC_EARG, "bx and by must both be 0 (library choice) or both set");
-    if (r.bx && !find_shape(r.bx, r.by))
-        return fail(JAC_EUNSUPPORTED, "no kernel for block shape %d x %d (see jacobi_tile_menu)",
-                    r.bx, r.by);
+    if (r.waves < 0)
+        return fail(JAC_EARG, "waves = %d is negative", r.waves);
+    if (r.bx && !find_shape(r.bx, r.by, r.waves))
+        return fail(JAC_EUNSUPPORTED,
+                    "no kernel for block shape %d x %d with %d waves (see jacobi_tile_menu)", r.bx,
+                    r.by, r.waves);
     if (r.t == 0)
         r.t = default_depth(dtype, kind);
     if (T > 0 && r.t > T)
@@ -306,6 +330,9 @@ int resolve_tile(int dtype, const jac_tile_t *tile, int T, jac_tile_t *out, cons
         const jac::TileShape &s = default_shape(dtype, kind, r.t);
         r.bx = s.bx();
         r.by = s.by();
+        r.waves = s.waves;
+    } else if (r.waves == 0) {
+        r.waves = find_shape(r.bx, r.by)->waves;
     }
     *out = r;
     return JAC_OK;
@@ -330,7 +357,7 @@ template <typename real>
 int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, int mode,
                const real *rhs, const TraceSink<real> &sink, hipStream_t st, int *npasses)
 {
-    const jac::TileShape *shape = find_shape(tile.bx, tile.by);
+    const jac::TileShape *shape = find_shape(tile.bx, tile.by, tile.waves);
     const int dtype = sizeof(real) == 8 ? JAC_F64 : JAC_F32;
     const int P = (T + tile.t - 1) / tile.t;
     const DeviceFacts dev = device_facts();
@@ -364,10 +391,15 @@ int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, in
         args.nz = (int)g.nz;
         args.nti = plan.nti;
         args.ntj = plan.ntj;
-        args.nkc = plan.nkc;
         args.hi = plan.hi;
         args.fstride = sink.F;
         args.kchunk = plan.kchunk;
+        if (debug_plans())
+            fprintf(stderr,
+                    "[jacobi] pass %d/%d depth %d block %dx%d w%d: columns %dx%d, k chunk %d planes, "
+                    "%d workgroups, occupancy %d/CU, %d CUs\n",
+                    pass + 1, P, depth, shape->bx(), shape->by(), shape->waves, plan.nti, plan.ntj,
+                    plan.kchunk, plan.nkc, occ, dev.cus);
         e = jac::launch_tblock<real>(shape->id, depth, mode, args, (int)plan.blocks(), st);
         if (e != hipSuccess)
             return hip_fail(e, "tblock launch");
@@ -426,15 +458,19 @@ struct GridPlan {
     int passes, tiles;
 };
 
-int plan_batch_grid(const jac_grid_t *g, int T, const jac_tile_t &tile, GridPlan *gp, int idx)
+int plan_batch_grid(int dtype, const jac_grid_t *g, int T, const jac_tile_t &tile, GridPlan *gp,
+                    int idx)
 {
     int rc;
     if ((rc = check_grid(g, &gp->geo)))
         return fail(rc, "grid %d: %s", idx, jacobi_last_error());
     if (T < 0)
         return fail(JAC_EARG, "grid %d: T = %d is negative", idx, T);
-    const jac::TileShape *shape = find_shape(tile.bx, tile.by);
+    const jac::TileShape *shape = find_shape(tile.bx, tile.by, tile.waves);
     const int t = tile.t;
+    if (shape_lds(dtype, *shape, t) + 1024 > device_facts().lds_per_block)
+        return fail(JAC_EUNSUPPORTED, "block %d x %d at depth %d needs more LDS than the device has",
+                    tile.bx, tile.by, t);
     if (!plan_ij(gp->geo, *shape, t, &gp->tp))
         return fail(JAC_EUNSUPPORTED, "block %d x %d has no valid cells at depth %d", tile.bx, tile.by, t);
     // a block's neighbours of the previous pass are the adjacent blocks only
@@ -701,7 +737,7 @@ static int batch_common(int dtype, int n, const jac_grid_t *g, const int *T, con
     GridPlan *plans = new GridPlan[n];
     BatchSizes z;
     for (int m = 0; m < n; ++m) {
-        if ((rc = plan_batch_grid(&g[m], T[m], *tl, &plans[m], m))) {
+        if ((rc = plan_batch_grid(dtype, &g[m], T[m], *tl, &plans[m], m))) {
             delete[] plans;
             return rc;
         }
@@ -780,7 +816,7 @@ int jacobi_batched_plan(int dtype, int n, const jac_grid_t *g, void *const *a, v
     h.n = n;
     h.nitems = z.nitems;
     h.ntiles = z.ntiles;
-    h.cfg = find_shape(tl.bx, tl.by)->id;
+    h.cfg = find_shape(tl.bx, tl.by, tl.waves)->id;
     h.t = tl.t;
     h.maxpasses = z.maxpasses;
     h.grids_off = (int64_t)align16(sizeof(jac::BatchHeader));
@@ -942,7 +978,7 @@ int jacobi_autotune(int dtype, const jac_grid_t *g, void *a, void *b, int T, int
     }
     const DeviceFacts dev = device_facts();
     float best = 1e30f;
-    jac_tile_t pick{0, 0, 0, 0};
+    jac_tile_t pick{0, 0, 0, 0, 0};
     int out = 0;
     for (int n = 0; n < kMenuN; ++n)
         for (int t = 1; t <= std::min(tmax, T); ++t) {
@@ -954,7 +990,7 @@ int jacobi_autotune(int dtype, const jac_grid_t *g, void *a, void *b, int T, int
             const int P = (T + t - 1) / t, dmax = T / P + (T % P ? 1 : 0);
             if (jac::tblock_scratch(dtype, s.id, dmax, jac::MODE_PLAIN) != 0)
                 continue;
-            jac_tile_t cand{t, s.bx(), s.by(), 0};
+            jac_tile_t cand{t, s.bx(), s.by(), 0, s.waves};
             if ((rc = jacobi_tblock(dtype, g, a, b, T, &cand, nullptr, stream, &out)))
                 break;  // warm-up; an error ends the search
             hipEventRecord(e0, st);
@@ -1005,16 +1041,17 @@ int jacobi_copy(void *dst, const void *src, size_t bytes, void *stream)
     return e == hipSuccess ? JAC_OK : hip_fail(e, "copy launch");
 }
 
-int jacobi_tile_menu(int dtype, int *pairs_host, int cap)
+int jacobi_tile_menu(int dtype, int *shapes_host, int cap)
 {
     g_err.clear();
     if (check_dtype(dtype))
         return JAC_EARG;
-    if (cap < 0 || (cap > 0 && !pairs_host))
+    if (cap < 0 || (cap > 0 && !shapes_host))
         return fail(JAC_EARG, "bad output array");
     for (int n = 0; n < kMenuN && n < cap; ++n) {
-        pairs_host[2 * n] = kMenu[n].bx();
-        pairs_host[2 * n + 1] = kMenu[n].by();
+        shapes_host[3 * n] = kMenu[n].bx();
+        shapes_host[3 * n + 1] = kMenu[n].by();
+        shapes_host[3 * n + 2] = kMenu[n].waves;
     }
     return kMenuN;
 }
@@ -1030,7 +1067,7 @@ int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, jac_tile_t
         return fail(JAC_EARG, "tile_host is NULL");
     if (T < 0)
         return fail(JAC_EARG, "T = %d is negative", T);
-    jac_tile_t req{t, 0, 0, 0};
+    jac_tile_t req{t, 0, 0, 0, 0};
     if ((rc = resolve_tile(dtype, &req, T, tile_host, &geo)))
         return rc;
     return JAC_OK;

@@ -16,7 +16,11 @@
     X(2, 1, 6, 8)        \
     X(3, 2, 3, 8)        \
     X(4, 1, 4, 8)        \
-    X(5, 2, 2, 8)
+    X(5, 2, 2, 8)        \
+    X(6, 1, 3, 16)       \
+    X(7, 1, 4, 16)       \
+    X(8, 2, 2, 16)       \
+    X(9, 1, 7, 8)
 
 namespace jac {
 
@@ -40,10 +44,10 @@ struct TbArgs {
     real *trace;
     int64_t sy, sz;
     int nx, ny, nz;
-    int nti, ntj, nkc;  // blocks along i, j, k
+    int nti, ntj;       // block columns along i and j
     int hi;             // i-halo (>= depth; even when CI is even, for alignment)
     int64_t fstride;    // MODE_TRACE: values per level of the face trace
-    int kchunk;         // output planes per block along k
+    int kchunk;         // output planes per workgroup along k
 };
 
 // A compiled kernel instance: entry point, dynamic LDS bytes, threads per block.

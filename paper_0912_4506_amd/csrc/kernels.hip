@@ -395,8 +395,10 @@ hipError_t launch_tblock(int cfg, int depth, int mode, const TbArgs<real> &p, in
     TbArgs<real> arg = p;
     void *args[] = {&arg};
     hipError_t e = hipLaunchKernel(ki.fn, dim3(nblocks), dim3(ki.threads), args, ki.lds, st);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // do not leave the error for the caller's next HIP call
         return e;
+    }
     return hipGetLastError();
 }
 
@@ -415,8 +417,10 @@ hipError_t launch_batched(int dtype, int cfg, int depth, const BatchLaunch &L, i
     BatchLaunch arg = L;
     void *args[] = {&arg};
     hipError_t e = hipLaunchKernel(ki.fn, dim3(nblocks), dim3(ki.threads), args, ki.lds, st);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // do not leave the error for the caller's next HIP call
         return e;
+    }
     return hipGetLastError();
 }
 

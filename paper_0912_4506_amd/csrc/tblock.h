@@ -89,12 +89,12 @@ constexpr size_t xch_bytes()
 // Loads clamp their coordinates into the array: cells outside it hold
 // garbage that only ever reaches other outside cells or shell cells, and
 // shell cells (i, j or k = 0 or n+1) pass their value through at every level.
-// One block (ti, tj, tk) of one pass at `depth` <= TL levels (the block
-// geometry is planned for TL; fewer levels leave the valid region valid).
-// xch: the block's LDS exchange buffer.
+// Output planes [k0, k1) of block column (ti, tj) for one pass at `depth`
+// <= TL levels (the block geometry is planned for TL; fewer levels leave the
+// valid region valid).  xch: the block's LDS exchange buffer.
 template <typename real, int TL, int CI, int R, int W, int MODE>
-__device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, int tk, int depth,
-                                        real *xch)
+__device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, int k0, int k1,
+                                        int depth, real *xch)
 {
     static_assert(TL >= 1 && TL <= JAC_MAX_DEPTH_DEV, "depth");
     const int lane = threadIdx.x & 63;
@@ -102,8 +102,6 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
 
     const AxisTile xi = axis_tile(ti, p.nx, 64 * CI, p.hi);
     const AxisTile xj = axis_tile(tj, p.ny, W * R, TL);
-    const int k0 = 1 + tk * p.kchunk;
-    const int k1 = min(k0 + p.kchunk, p.nz + 1);
     const int kstart = max(k0 - depth, 0);
     const int nsteps = ((k1 - 1 + depth) - kstart + 2) & ~1;  // rounded up to even
 
@@ -426,16 +424,22 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
     }
 }
 
+// One pass over a whole grid: workgroup (ti, tj, tk) streams output planes
+// [1 + tk*kchunk, 1 + (tk+1)*kchunk) of block column (ti, tj).  The k chunk
+// is the slowest index, so the workgroups that run at the same time stream
+// the same few planes of the grid: contiguous memory, which the DRAM serves
+// much faster than planes scattered over the grid.
 template <typename real, int TL, int CI, int R, int W, int MODE>
 __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
 {
     extern __shared__ unsigned char smem_raw[];
     real *xch = reinterpret_cast<real *>(smem_raw);  // [parity][W][2][TL][CI][64]
-    const int bid = xcd_remap(blockIdx.x, p.nti * p.ntj * p.nkc);
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int ti = bid % p.nti;
     const int tj = (bid / p.nti) % p.ntj;
     const int tk = bid / (p.nti * p.ntj);
-    tb_tile<real, TL, CI, R, W, MODE>(p, ti, tj, tk, TL, xch);
+    const int k0 = 1 + tk * p.kchunk;
+    tb_tile<real, TL, CI, R, W, MODE>(p, ti, tj, k0, min(k0 + p.kchunk, p.nz + 1), TL, xch);
 }
 
 // Batched pass over many grids (items of the plan).  In persistent mode each
@@ -518,12 +522,13 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
         p.nz = G.nz;
         p.nti = G.nti;
         p.ntj = G.ntj;
-        p.nkc = G.nkc;
         p.hi = G.hi;
         p.fstride = 0;
         p.kchunk = G.kchunk;
         const int depth = G.T / G.passes + (m.pass < G.T % G.passes ? 1 : 0);
-        tb_tile<real, TL, CI, R, W, MODE_PLAIN>(p, ti, tj, tk, depth, xch);
+        const int k0 = 1 + tk * G.kchunk;
+        tb_tile<real, TL, CI, R, W, MODE_PLAIN>(p, ti, tj, k0, min(k0 + G.kchunk, G.nz + 1), depth,
+                                                xch);
         if (!L.persistent)
             break;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

@@ -50,8 +50,8 @@ def _ptr(x):
     return ctypes.c_void_p(x.data_ptr()) if x is not None else None
 
 
-def _tile(t=None, bx=0, by=0, kchunk=0):
-    return Tile(int(t or 0), int(bx or 0), int(by or 0), int(kchunk or 0))
+def _tile(t=None, bx=0, by=0, kchunk=0, waves=0):
+    return Tile(int(t or 0), int(bx or 0), int(by or 0), int(kchunk or 0), int(waves or 0))
 
 
 def plain(a, b, T):
@@ -66,7 +66,7 @@ def plain(a, b, T):
     return b if out.value else a
 
 
-def tblock(a, b, T, t=None, bx=0, by=0, kchunk=0, rhs=None):
+def tblock(a, b, T, t=None, bx=0, by=0, kchunk=0, rhs=None, waves=0):
     """T sweeps fused t per pass (t=None: library choice).  With rhs, each
     sweep computes (six neighbours + rhs) / 6.  Returns the tensor holding
     level T."""
@@ -75,7 +75,7 @@ def tblock(a, b, T, t=None, bx=0, by=0, kchunk=0, rhs=None):
         _same(a, rhs)
     out = ctypes.c_int(0)
     lib = _lib.load()
-    tile = _tile(t, bx, by, kchunk)
+    tile = _tile(t, bx, by, kchunk, waves)
     with torch.cuda.device(a.device):
         check(lib.jacobi_tblock(dtype_code(a), ctypes.byref(grid_of(a)), _ptr(a), _ptr(b), int(T),
                                 ctypes.byref(tile), _ptr(rhs), _stream(a), ctypes.byref(out)))
@@ -93,20 +93,21 @@ def copy(dst, src):
 
 
 def tile_menu(dtype=torch.float64):
+    """Compiled block shapes: (bx, by, waves) triples."""
     lib = _lib.load()
-    buf = (ctypes.c_int * 64)()
-    n = lib.jacobi_tile_menu(_DTYPES[dtype], buf, 32)
+    buf = (ctypes.c_int * 192)()
+    n = lib.jacobi_tile_menu(_DTYPES[dtype], buf, 64)
     check(0 if n >= 0 else n)
-    return [(buf[2 * m], buf[2 * m + 1]) for m in range(n)]
+    return [(buf[3 * m], buf[3 * m + 1], buf[3 * m + 2]) for m in range(min(n, 64))]
 
 
 def default_tile(shape, T, t=0, dtype=torch.float64):
-    """Library choice of (t, bx, by, kchunk) for a (nz+2, ny+2, nx+2) grid."""
+    """Library choice of (t, bx, by, kchunk, waves) for a (nz+2, ny+2, nx+2) grid."""
     nz, ny, nx = (s - 2 for s in shape)
     tile = Tile()
     check(_lib.load().jacobi_default_tile(_DTYPES[dtype], ctypes.byref(Grid(nx, ny, nz, 0, 0)),
                                           int(T), int(t), ctypes.byref(tile)))
-    return tile.t, tile.bx, tile.by, tile.kchunk
+    return tile.t, tile.bx, tile.by, tile.kchunk, tile.waves
 
 
 def adjoint_workspace(like, t=0):
@@ -117,14 +118,14 @@ def adjoint_workspace(like, t=0):
     return torch.empty(n, dtype=torch.uint8, device=like.device)
 
 
-def adjoint(lam_a, lam_b, T, t=None, bx=0, by=0, kchunk=0, ws=None):
+def adjoint(lam_a, lam_b, T, t=None, bx=0, by=0, kchunk=0, ws=None, waves=0):
     """Adjoint of T sweeps.  lam_a holds dL/d(level T) (whole grid); returns the
     tensor (lam_a or lam_b) holding dL/d(level 0): interior and shell."""
     _same(lam_a, lam_b)
     if ws is None:
         ws = adjoint_workspace(lam_a, t or 0)
     out = ctypes.c_int(0)
-    tile = _tile(t, bx, by, kchunk)
+    tile = _tile(t, bx, by, kchunk, waves)
     with torch.cuda.device(lam_a.device):
         check(_lib.load().jacobi_adjoint(dtype_code(lam_a), ctypes.byref(grid_of(lam_a)),
                                          _ptr(lam_a), _ptr(lam_b), int(T), ctypes.byref(tile),
@@ -185,7 +186,7 @@ class BatchPlan:
 
     MODES = {"relaxed": _lib.JAC_BATCH_RELAXED, "lockstep": _lib.JAC_BATCH_LOCKSTEP}
 
-    def __init__(self, grids_a, grids_b, Ts, t=None, bx=0, by=0, kchunk=0):
+    def __init__(self, grids_a, grids_b, Ts, t=None, bx=0, by=0, kchunk=0, waves=0):
         n = len(grids_a)
         if n != len(grids_b) or n != len(Ts) or n == 0:
             raise ValueError("need equal, non-empty lists of a grids, b grids and sweep counts")
@@ -201,7 +202,7 @@ class BatchPlan:
         T = (ctypes.c_int * n)(*[int(v) for v in Ts])
         A = (ctypes.c_void_p * n)(*[x.data_ptr() for x in grids_a])
         B = (ctypes.c_void_p * n)(*[x.data_ptr() for x in grids_b])
-        tile = _tile(t, bx, by, kchunk)
+        tile = _tile(t, bx, by, kchunk, waves)
         nbytes = lib.jacobi_batched_plan_bytes(code, n, G, T, ctypes.byref(tile))
         if nbytes == 0:
             check(_lib.JAC_EARG)
@@ -230,15 +231,15 @@ class BatchPlan:
         return bool(self.ws[-4:].view(torch.int32).item())
 
 
-def batched(grids_a, grids_b, Ts, t=None, bx=0, by=0, kchunk=0, mode="relaxed"):
+def batched(grids_a, grids_b, Ts, t=None, bx=0, by=0, kchunk=0, mode="relaxed", waves=0):
     """Level T[m] of every grid m (one launch); returns the result tensors."""
-    return BatchPlan(grids_a, grids_b, Ts, t, bx, by, kchunk).run(mode).results()
+    return BatchPlan(grids_a, grids_b, Ts, t, bx, by, kchunk, waves).run(mode).results()
 
 
 def autotune(a, b, T, tmax=0, reps=2):
     """Time every block shape and depth for T sweeps on grids a, b (their
-    contents are overwritten); returns ((t, bx, by), ms) of the fastest and
-    makes it the library's choice for this geometry and T."""
+    contents are overwritten); returns ((t, bx, by, waves), ms) of the fastest
+    and makes it the library's choice for this geometry and T."""
     _same(a, b)
     best = Tile()
     ms = ctypes.c_float(0)
@@ -246,20 +247,21 @@ def autotune(a, b, T, tmax=0, reps=2):
         check(_lib.load().jacobi_autotune(dtype_code(a), ctypes.byref(grid_of(a)), _ptr(a), _ptr(b),
                                           int(T), int(tmax), int(reps), ctypes.byref(best),
                                           ctypes.byref(ms), _stream(a)))
-    return (best.t, best.bx, best.by), ms.value
+    return (best.t, best.bx, best.by, best.waves), ms.value
 
 
 def autotune_batch(grids_a, grids_b, Ts, candidates=None, mode="relaxed", reps=2):
     """Pick the (t, bx, by) of a batched run by timing the whole batch for
     each candidate (the grids' contents are overwritten).  Returns
-    ((t, bx, by), ms)."""
+    ((t, bx, by, waves), ms)."""
     if candidates is None:
-        candidates = [(t, bx, by) for (bx, by) in tile_menu(grids_a[0].dtype) for t in range(2, 7)]
+        candidates = [(t, bx, by, w) for (bx, by, w) in tile_menu(grids_a[0].dtype)
+                      for t in range(2, 7)]
     best, best_ms = None, float("inf")
     st = torch.cuda.current_stream(grids_a[0].device)
-    for (t, bx, by) in candidates:
+    for (t, bx, by, w) in candidates:
         try:
-            plan = BatchPlan(grids_a, grids_b, Ts, t=t, bx=bx, by=by)
+            plan = BatchPlan(grids_a, grids_b, Ts, t=t, bx=bx, by=by, waves=w)
             plan.run(mode)
         except _lib.JacobiError:
             continue
@@ -272,5 +274,5 @@ def autotune_batch(grids_a, grids_b, Ts, candidates=None, mode="relaxed", reps=2
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         if ms < best_ms:
-            best, best_ms = (t, bx, by), ms
+            best, best_ms = (t, bx, by, w), ms
     return best, best_ms

@@ -67,22 +67,24 @@ def test_tile_checks(lib):
         return lib.jacobi_tblock(1, ctypes.byref(g), A, B, 5, ctypes.byref(tile), None, None,
                                  ctypes.byref(OUT))
 
-    assert tb(Tile(9, 0, 0, 0)) == JAC_EARG and "depth" in err(lib)
-    assert tb(Tile(4, 100, 0, 0)) == JAC_EARG
-    assert tb(Tile(4, 100, 100, 0)) == JAC_EUNSUPPORTED and "menu" in err(lib)
-    assert tb(Tile(2, 0, 0, -1)) == JAC_EARG and "kchunk" in err(lib)
+    assert tb(Tile(9, 0, 0, 0, 0)) == JAC_EARG and "depth" in err(lib)
+    assert tb(Tile(4, 100, 0, 0, 0)) == JAC_EARG
+    assert tb(Tile(4, 100, 100, 0, 0)) == JAC_EUNSUPPORTED and "menu" in err(lib)
+    assert tb(Tile(4, 64, 48, 0, 5)) == JAC_EUNSUPPORTED and "waves" in err(lib)
+    assert tb(Tile(2, 0, 0, -1, 0)) == JAC_EARG and "kchunk" in err(lib)
 
 
 def test_menu_and_default_tile(lib):
-    buf = (ctypes.c_int * 64)()
-    n = lib.jacobi_tile_menu(1, buf, 32)
+    buf = (ctypes.c_int * 192)()
+    n = lib.jacobi_tile_menu(1, buf, 64)
     assert n >= 2
-    pairs = [(buf[2 * m], buf[2 * m + 1]) for m in range(n)]
-    assert all(bx % 64 == 0 and by > 0 for bx, by in pairs)
+    shapes = [(buf[3 * m], buf[3 * m + 1], buf[3 * m + 2]) for m in range(n)]
+    assert all(bx % 64 == 0 and by > 0 and w in (4, 8, 16) for bx, by, w in shapes)
+    assert len(set(shapes)) == len(shapes)
     t = Tile()
     assert lib.jacobi_default_tile(1, ctypes.byref(Grid(512, 512, 512, 0, 0)), 100, 0,
                                    ctypes.byref(t)) == 0
-    assert 1 <= t.t <= 8 and (t.bx, t.by) in pairs
+    assert 1 <= t.t <= 8 and (t.bx, t.by, t.waves) in shapes
     # depth never exceeds the sweep count
     assert lib.jacobi_default_tile(1, ctypes.byref(Grid(9, 9, 9, 0, 0)), 3, 8, ctypes.byref(t)) == 0
     assert t.t == 3
@@ -93,7 +95,7 @@ def test_adjoint_workspace_checks(lib):
     need = lib.jacobi_adjoint_workspace(1, ctypes.byref(g), 4)
     faces = 2 * (11 * 12 + 10 * 12 + 10 * 11)
     assert need == (2 + 4) * faces * 8
-    tile = Tile(4, 0, 0, 0)
+    tile = Tile(4, 0, 0, 0, 0)
     rc = lib.jacobi_adjoint(1, ctypes.byref(g), A, B, 5, ctypes.byref(tile), None, 0, None,
                             ctypes.byref(OUT))
     assert rc == JAC_EWORKSPACE

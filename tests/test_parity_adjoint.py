@@ -30,12 +30,17 @@ def test_adjoint_fp64_bitwise(jac, shape, T, t):
     nx, ny, nz = shape
     lam = inputs.grid(nx, ny, nz, seed=7)
     ref = oracle.adjoint(lam, T)
-    for bx, by in jac.tile_menu(torch.float64):
+    for bx, by, w in jac.tile_menu(torch.float64):
         hi = t + (t % 2) if bx % 128 == 0 else t
         if bx - 2 * hi < 1 or by - 2 * t < 1:
             continue
-        got = gpu_adjoint(jac, lam, T, t=t, bx=bx, by=by)
-        assert np.array_equal(got, ref), (shape, T, t, bx, by)
+        from paper_0912_4506_amd._lib import JacobiError, JAC_EUNSUPPORTED
+        try:
+            got = gpu_adjoint(jac, lam, T, t=t, bx=bx, by=by, waves=w)
+        except JacobiError as e:   # block refused at this depth (LDS)
+            assert e.code == JAC_EUNSUPPORTED
+            continue
+        assert np.array_equal(got, ref), (shape, T, t, bx, by, w)
 
 
 def test_adjoint_fp32(jac):
