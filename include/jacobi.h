@@ -216,8 +216,11 @@ int jacobi_autotune(int dtype, const jac_grid_t *g, void *a, void *b, int T,
 int jacobi_tile_menu(int dtype, int *shapes_host, int cap);
 
 /* The tile jacobi_tblock uses for (dtype, g, T, t) when tile fields are 0
- * (t = 0: library choice of t as well).  Writes *tile_host; returns JAC_OK. */
-int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t,
+ * (t = 0: library choice of t as well); rhs != 0 asks for the choice made
+ * when a right-hand side is passed (those kernels hold one more value per
+ * cell and level, so their register budget differs).  Only nx, ny, nz of *g
+ * are read.  Writes *tile_host; returns JAC_OK. */
+int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, int rhs,
                         jac_tile_t *tile_host);
 
 #ifdef __cplusplus

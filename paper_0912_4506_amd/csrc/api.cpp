@@ -1056,7 +1056,7 @@ int jacobi_tile_menu(int dtype, int *shapes_host, int cap)
     return kMenuN;
 }
 
-int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, jac_tile_t *tile_host)
+int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, int rhs, jac_tile_t *tile_host)
 {
     g_err.clear();
     Geo geo;
@@ -1068,7 +1068,8 @@ int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, jac_tile_t
     if (T < 0)
         return fail(JAC_EARG, "T = %d is negative", T);
     jac_tile_t req{t, 0, 0, 0, 0};
-    if ((rc = resolve_tile(dtype, &req, T, tile_host, &geo)))
+    if ((rc = resolve_tile(dtype, &req, T, tile_host, rhs ? nullptr : &geo,
+                           rhs ? KIND_RHS : KIND_PLAIN)))
         return rc;
     return JAC_OK;
 }

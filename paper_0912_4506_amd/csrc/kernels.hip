@@ -138,36 +138,89 @@ __global__ void copy_shell_kernel(const real *__restrict__ a, real *__restrict__
 // Residual of the Laplace system whose fixed point the Jacobi iteration seeks:
 // r = (six neighbours of x, summed left to right) - 6x on the interior, FP64,
 // i.e. b - A x for A = 6I - adjacency with the shell of x as Dirichlet data.
-// Writes (float)r to r32 (interior) and a per-block partial sum of r^2.  Blocks own row strips
-// of RES_ROWS rows x 256 cells and a k chunk; each thread sums its cells in
-// order, the block sums its threads with a fixed tree.
-constexpr int RES_ROWS = 4;
-constexpr int RES_KC = 16;
-
-__global__ __launch_bounds__(256) void residual_kernel(const double *__restrict__ x,
+// Writes (float)r to r32 (interior) and a per-block partial sum of r^2.
+// Same strip structure as the plain sweep (PLAIN_ROWS rows x 512 cells per
+// block, k streamed with the strip's k-1, k, k+1 rows in registers); each
+// thread sums its cells' r^2 in stream order, the block sums its threads with
+// a fixed tree, so the result is the same run to run.
+__global__ __launch_bounds__(256) void residual_kernel(const double *__restrict__ X,
                                                        float *__restrict__ r32,
-                                                       double *__restrict__ partial, GridArgs g)
+                                                       double *__restrict__ partial, PlainArgs p)
 {
+    constexpr int RB = PLAIN_ROWS;
     __shared__ double red[256];
-    const int64_t i = 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t j0 = 1 + (int64_t)blockIdx.y * RES_ROWS;
-    const int64_t k0 = 1 + (int64_t)blockIdx.z * RES_KC;
+    const int i0 = 1 + blockIdx.x * 512 + 2 * threadIdx.x;
+    const int j0 = 1 + blockIdx.y * RB;
+    const int k0 = 1 + blockIdx.z * p.kchunk;
+    const int k1 = min(k0 + p.kchunk, p.nz + 1);
+    const int ia = min(i0, p.nx + 1), ib = min(i0 + 1, p.nx + 1);
+    const int iw = min(i0 - 1, p.nx + 1), ie = min(i0 + 2, p.nx + 1);
+    int64_t ro[RB + 2];
+#pragma unroll
+    for (int r = 0; r < RB + 2; ++r)
+        ro[r] = (int64_t)min(j0 - 1 + r, p.ny + 1) * p.sy;
+    auto load = [&](int k, double(&c)[RB + 2][2], double(&w)[RB], double(&e)[RB]) {
+        const double *pl = X + (int64_t)min(k, p.nz + 1) * p.sz;
+#pragma unroll
+        for (int r = 0; r < RB + 2; ++r) {
+            c[r][0] = pl[ro[r] + ia];
+            c[r][1] = pl[ro[r] + ib];
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            w[r] = pl[ro[r + 1] + iw];
+            e[r] = pl[ro[r + 1] + ie];
+        }
+    };
+    double prev[RB][2], cur[RB + 2][2], cw[RB], ce[RB], nxt[RB + 2][2], nw[RB], ne[RB];
+    load(k0 - 1, nxt, nw, ne);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        prev[r][0] = nxt[r + 1][0];
+        prev[r][1] = nxt[r + 1][1];
+    }
+    load(k0, cur, cw, ce);
     double acc = 0.0;
-    if (i <= g.nx) {
-        for (int64_t k = k0; k < k0 + RES_KC && k <= g.nz; ++k)
-            for (int64_t j = j0; j < j0 + RES_ROWS && j <= g.ny; ++j) {
-                const int64_t o = i + j * g.sy + k * g.sz;
-                double s = x[o - 1];
-                s = s + x[o + 1];
-                s = s + x[o - g.sy];
-                s = s + x[o + g.sy];
-                s = s + x[o - g.sz];
-                s = s + x[o + g.sz];
-                const double six_x = 6.0 * x[o];
-                const double v = s - six_x;
-                r32[o] = (float)v;
-                acc = acc + v * v;
+    for (int k = k0; k < k1; ++k) {
+        load(k + 1, nxt, nw, ne);
+        float *out = r32 + (int64_t)k * p.sz;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            double s0 = cw[r] + cur[r + 1][1];
+            s0 = s0 + cur[r][0];
+            s0 = s0 + cur[r + 2][0];
+            s0 = s0 + prev[r][0];
+            s0 = s0 + nxt[r + 1][0];
+            double s1 = cur[r + 1][0] + ce[r];
+            s1 = s1 + cur[r][1];
+            s1 = s1 + cur[r + 2][1];
+            s1 = s1 + prev[r][1];
+            s1 = s1 + nxt[r + 1][1];
+            const double six0 = 6.0 * cur[r + 1][0], six1 = 6.0 * cur[r + 1][1];
+            const double v0 = s0 - six0, v1 = s1 - six1;
+            if (j0 + r <= p.ny) {
+                if (i0 <= p.nx) {
+                    out[ro[r + 1] + i0] = (float)v0;
+                    acc = acc + v0 * v0;
+                }
+                if (i0 + 1 <= p.nx) {
+                    out[ro[r + 1] + i0 + 1] = (float)v1;
+                    acc = acc + v1 * v1;
+                }
             }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            prev[r][0] = cur[r + 1][0];
+            prev[r][1] = cur[r + 1][1];
+            cw[r] = nw[r];
+            ce[r] = ne[r];
+        }
+#pragma unroll
+        for (int r = 0; r < RB + 2; ++r) {
+            cur[r][0] = nxt[r][0];
+            cur[r][1] = nxt[r][1];
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -179,6 +232,11 @@ __global__ __launch_bounds__(256) void residual_kernel(const double *__restrict_
     if (threadIdx.x == 0)
         partial[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
 }
+
+// Fill and update kernels: blocks own RES_ROWS rows x 256 cells and a k chunk
+// of RES_KC planes, one cell per thread per row
+constexpr int RES_ROWS = 4;
+constexpr int RES_KC = 16;
 
 // norm2 = sum of the n partials: each thread sums a strided subset in order,
 // then a fixed tree over the 256 threads
@@ -485,17 +543,26 @@ static dim3 strip_grid(const GridArgs &g)
                 (unsigned)((g.nz + RES_KC - 1) / RES_KC));
 }
 
+// Residual geometry: row strips like the plain sweep, k chunks of RES_KCHUNK
+static constexpr int RES_KCHUNK = 64;
+static dim3 residual_grid(const GridArgs &g)
+{
+    return dim3((unsigned)((g.nx + 511) / 512), (unsigned)((g.ny + PLAIN_ROWS - 1) / PLAIN_ROWS),
+                (unsigned)((g.nz + RES_KCHUNK - 1) / RES_KCHUNK));
+}
+
 int64_t residual_partials(const GridArgs &g)
 {
-    const dim3 d = strip_grid(g);
+    const dim3 d = residual_grid(g);
     return (int64_t)d.x * d.y * d.z;
 }
 
 hipError_t launch_residual(const double *x, float *r32, double *partial, double *norm2,
                            const GridArgs &g, hipStream_t st)
 {
-    const dim3 grid = strip_grid(g);
-    hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, st, x, r32, partial, g);
+    const dim3 grid = residual_grid(g);
+    PlainArgs p{(int)g.nx, (int)g.ny, (int)g.nz, RES_KCHUNK, g.sy, g.sz};
+    hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, st, x, r32, partial, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
@@ -504,9 +571,42 @@ hipError_t launch_residual(const double *x, float *r32, double *partial, double 
     return hipGetLastError();
 }
 
+hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStream_t st)
+{
+    hipLaunchKernelGGL(update_kernel, strip_grid(g), dim3(256), 0, st, x, e32, g);
+    return hipGetLastError();
+}
+
+// a dense grid is one contiguous run of span elements: fill it flat
+template <typename real>
+__global__ __launch_bounds__(256) void flat_fill_kernel(real *__restrict__ x, int64_t n, real v)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    constexpr int PER = 16 / sizeof(real);
+    const int64_t base = t * PER;
+    if (base + PER <= n) {
+        typedef real vec __attribute__((ext_vector_type(PER)));
+        vec w;
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            w[q] = v;
+        *reinterpret_cast<vec *>(x + base) = w;
+    } else {
+        for (int64_t q = base; q < n; ++q)
+            x[q] = v;
+    }
+}
+
 template <typename real>
 hipError_t launch_grid_fill(real *x, real v, const GridArgs &g, hipStream_t st)
 {
+    if (g.sy == g.nx + 2 && g.sz == g.sy * (g.ny + 2) && ((uintptr_t)x % 16) == 0) {
+        const int64_t n = g.sz * (g.nz + 2);
+        const int64_t per = 16 / (int64_t)sizeof(real);
+        const int64_t blocks = ((n + per - 1) / per + 255) / 256;
+        hipLaunchKernelGGL(flat_fill_kernel<real>, dim3((unsigned)blocks), dim3(256), 0, st, x, n, v);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((g.nx + 2 + 255) / 256), (unsigned)((g.ny + 2 + RES_ROWS - 1) / RES_ROWS),
                     (unsigned)((g.nz + 2 + RES_KC - 1) / RES_KC));
     hipLaunchKernelGGL(grid_fill_kernel<real>, grid, dim3(256), 0, st, x, v, g);
@@ -514,12 +614,6 @@ hipError_t launch_grid_fill(real *x, real v, const GridArgs &g, hipStream_t st)
 }
 template hipError_t launch_grid_fill<float>(float *, float, const GridArgs &, hipStream_t);
 template hipError_t launch_grid_fill<double>(double *, double, const GridArgs &, hipStream_t);
-
-hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStream_t st)
-{
-    hipLaunchKernelGGL(update_kernel, strip_grid(g), dim3(256), 0, st, x, e32, g);
-    return hipGetLastError();
-}
 
 static int grid_blocks(int64_t n)
 {

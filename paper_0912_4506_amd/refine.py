@@ -19,11 +19,14 @@ import torch
 from . import jacobi
 
 
-def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, callback=None):
+def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, callback=None,
+                 bx=0, by=0, waves=0):
     """Solve in place.  x: float64 GPU grid (shell = Dirichlet data, interior
     = initial guess).  Returns (x, outer_iterations, relative_residual).
     ``check_every`` > 1 reads the norm only every that many outer iterations
-    (fewer host synchronisations; the stopping point is then a multiple)."""
+    (fewer host synchronisations; the stopping point is then a multiple).
+    t, bx, by, waves: blocking of the inner FP32 sweeps (t=None and 0: the
+    library's choice)."""
     if x.dtype != torch.float64:
         raise TypeError("x must be float64")
     r32 = torch.empty(x.shape, dtype=torch.float32, device=x.device)
@@ -47,15 +50,16 @@ def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, ca
             if rel <= tol or it >= max_outer:
                 break
         jacobi.fill(e_a, 0.0)
-        e = jacobi.tblock(e_a, e_b, inner, t=t, rhs=r32)
+        e = jacobi.tblock(e_a, e_b, inner, t=t, bx=bx, by=by, waves=waves, rhs=r32)
         jacobi.update_f64(x, e)
         it += 1
     return x, it, rel
 
 
-def jacobi_solve_f64(x, tol=1e-10, check=50, t=8, max_sweeps=10**9, callback=None):
+def jacobi_solve_f64(x, tol=1e-10, check=50, t=None, max_sweeps=10**9, callback=None):
     """All-FP64 Jacobi (the update of Sect. 1.1) to |r| <= tol |r0|, the
-    residual checked every ``check`` sweeps.  Returns (x, sweeps, rel)."""
+    residual checked every ``check`` sweeps.  Returns (x, sweeps, rel).
+    t: sweeps per blocked pass (None: the library's choice; 1: plain)."""
     if x.dtype != torch.float64:
         raise TypeError("x must be float64")
     a = x
@@ -68,7 +72,7 @@ def jacobi_solve_f64(x, tol=1e-10, check=50, t=8, max_sweeps=10**9, callback=Non
     rel = 1.0
     sweeps = 0
     while rel > tol and sweeps < max_sweeps:
-        out = jacobi.tblock(a, b, check, t=t) if t and t > 1 else jacobi.plain(a, b, check)
+        out = jacobi.plain(a, b, check) if t == 1 else jacobi.tblock(a, b, check, t=t)
         if out is b:
             a, b = b, a
         sweeps += check

@@ -82,11 +82,13 @@ def test_menu_and_default_tile(lib):
     assert all(bx % 64 == 0 and by > 0 and w in (4, 8, 16) for bx, by, w in shapes)
     assert len(set(shapes)) == len(shapes)
     t = Tile()
-    assert lib.jacobi_default_tile(1, ctypes.byref(Grid(512, 512, 512, 0, 0)), 100, 0,
-                                   ctypes.byref(t)) == 0
-    assert 1 <= t.t <= 8 and (t.bx, t.by, t.waves) in shapes
+    for rhs in (0, 1):
+        assert lib.jacobi_default_tile(1, ctypes.byref(Grid(512, 512, 512, 0, 0)), 100, 0, rhs,
+                                       ctypes.byref(t)) == 0
+        assert 1 <= t.t <= 8 and (t.bx, t.by, t.waves) in shapes
     # depth never exceeds the sweep count
-    assert lib.jacobi_default_tile(1, ctypes.byref(Grid(9, 9, 9, 0, 0)), 3, 8, ctypes.byref(t)) == 0
+    assert lib.jacobi_default_tile(1, ctypes.byref(Grid(9, 9, 9, 0, 0)), 3, 8, 0,
+                                   ctypes.byref(t)) == 0
     assert t.t == 3
 
 

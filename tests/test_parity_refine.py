@@ -17,7 +17,7 @@ def dev(u, dtype=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(u)).to("cuda", dtype)
 
 
-@pytest.mark.parametrize("shape", [(30, 17, 23), (300, 5, 9), (1, 1, 1), (257, 40, 20)])
+@pytest.mark.parametrize("shape", [(30, 17, 23), (300, 5, 9), (1, 1, 1), (257, 40, 20), (530, 19, 70)])
 def test_residual_f64(jac, shape):
     nx, ny, nz = shape
     x = inputs.grid(nx, ny, nz, seed=4)
@@ -49,6 +49,20 @@ def test_update_and_fill(jac):
     assert np.array_equal(xt.cpu().numpy(), ref)
     jac.fill(et, 0.0)
     assert torch.count_nonzero(et).item() == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_fill_dense_and_strided(jac, dtype):
+    # dense grids take the flat path (odd element count: a ragged tail);
+    # a padded view takes the row path and leaves the padding alone
+    dense = torch.ones((5, 3, 7), dtype=dtype, device="cuda")
+    jac.fill(dense, 2.5)
+    assert torch.all(dense == 2.5).item()
+    base = torch.ones((9, 8, 11), dtype=dtype, device="cuda")
+    view = base[:, :, :7]
+    jac.fill(view, -1.0)
+    assert torch.all(view == -1.0).item()
+    assert torch.all(base[:, :, 7:] == 1.0).item()
 
 
 @pytest.mark.parametrize("dtype,t", [(torch.float64, 4), (torch.float64, 8), (torch.float32, 8)])

@@ -62,3 +62,45 @@ def test_pass_planning_and_roofline():
     assert pm.roofline(8e12, 100, 1) == pytest.approx(5e11)
     assert pm.roofline(8e12, 100, 4) == pytest.approx(2e12)
     assert pm.redundancy_overlapped(48, 48, 8) == pytest.approx((64 * 64) / (48 * 48))
+
+
+@pytest.mark.parametrize("shape,tol,check,modes,seed,zero", [
+    ((10, 9, 12), 1e-10, 1, 16, 0, True),    # every mode kept
+    ((40, 33, 37), 1e-10, 1, 3, 0, True),    # truncated projection
+    ((5, 1, 3), 1e-10, 1, 16, 0, True),      # a 1-cell axis
+    ((12, 7, 9), 1e-9, 1, 2, 5, False),      # random initial interior
+    ((12, 7, 9), 1e-9, 50, 2, 5, False),     # checked every 50 sweeps
+])
+def test_sweeps_to_tolerance_matches_oracle_solve(oracle_mod, shape, tol, check, modes, seed,
+                                                  zero):
+    """The spectral sweep count against a real Jacobi solve by the oracle,
+    which checks its FP64 residual every ``check`` sweeps."""
+    from paper_0912_4506_amd import inputs
+    g = (inputs.laplace_problem if zero else inputs.grid)(*shape, seed=seed)
+    _, sweeps, rel, ok = oracle_mod.jacobi_solve(g, tol, check_every=check)
+    assert ok and rel <= tol
+    got = pm.jacobi_sweeps_to_tolerance(g, tol, check_every=check, modes=modes)
+    assert abs(got - sweeps) <= check
+
+
+def test_sweeps_to_tolerance_single_mode():
+    """Initial residual = one discrete sine mode: |r_s| = |lambda|^s |r_0|."""
+    import math
+    import numpy as np
+    nx, ny, nz = 9, 6, 7
+    a, b, c = 2, 1, 3
+    i = np.arange(1, nx + 1)
+    j = np.arange(1, ny + 1)
+    k = np.arange(1, nz + 1)
+    mode = (np.sin(math.pi * c * k / (nz + 1))[:, None, None]
+            * np.sin(math.pi * b * j / (ny + 1))[None, :, None]
+            * np.sin(math.pi * a * i / (nx + 1))[None, None, :])
+    lam = (math.cos(math.pi * a / (nx + 1)) + math.cos(math.pi * b / (ny + 1))
+           + math.cos(math.pi * c / (nz + 1))) / 3
+    # x0 with zero shell and interior x: r0 = -(A x) = -(6 - 6 lam) x
+    x0 = np.zeros((nz + 2, ny + 2, nx + 2))
+    x0[1:-1, 1:-1, 1:-1] = mode
+    tol = 1e-6
+    want = math.ceil(math.log(tol) / math.log(abs(lam)) - 1e-9)
+    assert pm.jacobi_sweeps_to_tolerance(x0, tol, modes=1) == want
+    assert pm.jacobi_sweeps_to_tolerance(x0, tol, check_every=7) == -(-want // 7) * 7
