@@ -247,13 +247,13 @@ bool tuned(int dtype, const Geo &g, int T, jac_tile_t *out)
 // What a blocking choice is for: the kind of kernel it selects.
 enum { KIND_PLAIN = 0, KIND_RHS = 1, KIND_TRACE = 2, KIND_BATCH = 3 };
 
-// Untuned default depth, from 512^3 (single grid) and 64-grid batch runs on
-// MI355X.
+// Untuned default depth, from 512^3 (single grid), 768^3 (right-hand side)
+// and 64-grid batch runs on MI355X.
 int default_depth(int dtype, int kind)
 {
     if (dtype == JAC_F64)
         return kind == KIND_BATCH ? 5 : 4;
-    return 6;
+    return kind == KIND_RHS ? 5 : 6;
 }
 
 // Per-lane scratch bytes (register spills) of the kernel a choice selects;
@@ -267,15 +267,38 @@ int kind_scratch(int dtype, int kind, int cfg, int depth)
     return jac::tblock_scratch(dtype, cfg, depth, mode);
 }
 
-// Untuned default block shape: the first of a preference order (measured on
-// 512^3 FP64 runs) that has valid cells at depth t and compiles without
-// register spills for this kind of kernel.
+// Block shapes measured fastest on MI355X at a given depth: 512^3 sweeps
+// without a right-hand side (T = 100) and 768^3 FP32 sweeps with one (T = 50).
+// Some of these spill a few registers and are still the fastest.
+struct MeasuredShape {
+    int dtype, kind, t, bx, by, waves;
+};
+const MeasuredShape kMeasured[] = {
+    {JAC_F64, KIND_PLAIN, 3, 64, 64, 8},  {JAC_F64, KIND_PLAIN, 4, 64, 56, 8},
+    {JAC_F64, KIND_PLAIN, 5, 64, 32, 8},  {JAC_F64, KIND_PLAIN, 6, 64, 32, 8},
+    {JAC_F32, KIND_PLAIN, 4, 64, 64, 16}, {JAC_F32, KIND_PLAIN, 5, 64, 64, 16},
+    {JAC_F32, KIND_PLAIN, 6, 64, 64, 16}, {JAC_F32, KIND_PLAIN, 7, 64, 64, 8},
+    {JAC_F32, KIND_PLAIN, 8, 64, 48, 16}, {JAC_F32, KIND_RHS, 4, 64, 56, 8},
+    {JAC_F32, KIND_RHS, 5, 64, 64, 16},   {JAC_F32, KIND_RHS, 6, 64, 48, 16},
+    {JAC_F32, KIND_RHS, 7, 64, 48, 8},    {JAC_F32, KIND_RHS, 8, 64, 48, 8},
+};
+
+// Untuned default block shape: the measured one for (dtype, kind, t) if there
+// is one, else the first of a preference order that has valid cells at depth
+// t and compiles without register spills for this kind of kernel.
 const jac::TileShape &default_shape(int dtype, int kind, int t)
 {
-    static const int pref[][3] = {{64, 56, 8},   {64, 48, 8},  {64, 48, 16}, {64, 64, 8},
-                                  {64, 64, 16},  {128, 32, 8}, {128, 32, 16}, {64, 32, 8},
-                                  {128, 24, 8},  {128, 16, 8}};
-    for (const auto &p : pref) {
+    for (const auto &m : kMeasured)
+        if (m.dtype == dtype && m.kind == kind && m.t == t)
+            if (const jac::TileShape *s = find_shape(m.bx, m.by, m.waves))
+                return *s;
+    static const int pref64[][3] = {{64, 56, 8},  {64, 48, 8},  {64, 48, 16},  {64, 64, 8},
+                                    {64, 64, 16}, {128, 32, 8}, {128, 32, 16}, {64, 32, 8},
+                                    {128, 24, 8}, {128, 16, 8}};
+    static const int pref32[][3] = {{64, 64, 16}, {64, 64, 8},  {64, 56, 8},   {64, 48, 16},
+                                    {64, 48, 8},  {128, 32, 8}, {128, 32, 16}, {64, 32, 8},
+                                    {128, 24, 8}, {128, 16, 8}};
+    for (const auto &p : dtype == JAC_F64 ? pref64 : pref32) {
         const jac::TileShape *s = find_shape(p[0], p[1], p[2]);
         if (!s)
             continue;

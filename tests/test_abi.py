@@ -79,7 +79,7 @@ def test_menu_and_default_tile(lib):
     n = lib.jacobi_tile_menu(1, buf, 64)
     assert n >= 2
     shapes = [(buf[3 * m], buf[3 * m + 1], buf[3 * m + 2]) for m in range(n)]
-    assert all(bx % 64 == 0 and by > 0 and w in (4, 8, 16) for bx, by, w in shapes)
+    assert all(bx % 64 == 0 and by > 0 and w in (4, 8, 12, 16) for bx, by, w in shapes)
     assert len(set(shapes)) == len(shapes)
     t = Tile()
     for rhs in (0, 1):
