@@ -182,11 +182,23 @@ int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws,
  *   to run.  x and r32 share the geometry g (r32 holds floats).  ws: device
  *   workspace of at least jacobi_residual_workspace(g) bytes, 8-byte aligned.
  * jacobi_update_f64: x += (double)e32 on the interior.
+ * jacobi_update_residual_f64: the update and the next residual in one pass
+ *   over memory: x_new = x + (double)e32 on the interior (x_new's shell is
+ *   not written: the caller keeps it equal to x's), then r32 and *norm2 as
+ *   jacobi_residual_f64 computes them for x_new, and zero32's interior set to
+ *   0 (zero32 is typically the next inner solve's starting guess).  x, e32,
+ *   x_new, r32, zero32, norm2 and ws must not overlap (JAC_EARG); results
+ *   are bitwise those of jacobi_update_f64 followed by jacobi_residual_f64
+ *   (the norm's summation order differs).  ws as for jacobi_residual_f64.
  * jacobi_fill: every element of a grid, shell included, set to `value`
  *   (converted to the grid's dtype). */
 size_t jacobi_residual_workspace(const jac_grid_t *g);
 int jacobi_residual_f64(const jac_grid_t *g, const double *x, float *r32,
                         double *norm2, void *ws, size_t ws_bytes, void *stream);
+int jacobi_update_residual_f64(const jac_grid_t *g, const double *x,
+                               const float *e32, double *x_new, float *r32,
+                               float *zero32, double *norm2, void *ws,
+                               size_t ws_bytes, void *stream);
 int jacobi_update_f64(const jac_grid_t *g, double *x, const float *e32,
                       void *stream);
 int jacobi_fill(int dtype, const jac_grid_t *g, void *x, double value,

@@ -711,6 +711,38 @@ int jacobi_residual_f64(const jac_grid_t *g, const double *x, float *r32, double
     return e == hipSuccess ? JAC_OK : hip_fail(e, "residual launch");
 }
 
+int jacobi_update_residual_f64(const jac_grid_t *g, const double *x, const float *e32,
+                               double *x_new, float *r32, float *zero32, double *norm2, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_grid(g, &geo)) || (rc = check_ptr(x, JAC_F64, "x")) ||
+        (rc = check_ptr(e32, JAC_F32, "e32")) || (rc = check_ptr(x_new, JAC_F64, "x_new")) ||
+        (rc = check_ptr(r32, JAC_F32, "r32")) || (rc = check_ptr(zero32, JAC_F32, "zero32")) ||
+        (rc = check_ptr(norm2, JAC_F64, "norm2")))
+        return rc;
+    const size_t need = (size_t)jac::residual_partials(grid_args(geo)) * sizeof(double);
+    if (!ws)
+        return fail(JAC_EWORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+    if (ws_bytes < need)
+        return fail(JAC_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    if ((uintptr_t)ws % 8)
+        return fail(JAC_EARG, "workspace is not 8-byte aligned");
+    const size_t xb = (size_t)geo.span * 8, fb = (size_t)geo.span * 4;
+    const void *buf[] = {x, e32, x_new, r32, zero32, norm2, ws};
+    const size_t len[] = {xb, fb, xb, fb, fb, 8, need};
+    for (int u = 0; u < 7; ++u)
+        for (int v = u + 1; v < 7; ++v)
+            if (overlap(buf[u], len[u], buf[v], len[v]))
+                return fail(JAC_EARG,
+                            "x, e32, x_new, r32, zero32, norm2 and the workspace must not overlap");
+    hipError_t e = jac::launch_update_residual(x, e32, x_new, zero32, r32, (double *)ws, norm2,
+                                               grid_args(geo), (hipStream_t)stream);
+    return e == hipSuccess ? JAC_OK : hip_fail(e, "update-residual launch");
+}
+
 int jacobi_update_f64(const jac_grid_t *g, double *x, const float *e32, void *stream)
 {
     g_err.clear();

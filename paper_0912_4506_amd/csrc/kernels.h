@@ -132,10 +132,14 @@ hipError_t launch_faces(int op, real *grid, real *G, real *S, const real *tr, co
                         int64_t F, int depth, hipStream_t st);
 
 // Refinement helpers: FP64 residual (r32 = (float)r, norm2 = |r|^2
-// through residual_partials(g) per-block partial sums) and x += e32.
+// through residual_partials(g) per-block partial sums), x += e32, and the
+// fused form: xnew = x + e32, the residual of xnew, z = 0 (interiors).
 int64_t residual_partials(const GridArgs &g);
 hipError_t launch_residual(const double *x, float *r32, double *partial, double *norm2,
                            const GridArgs &g, hipStream_t st);
+hipError_t launch_update_residual(const double *x, const float *e32, double *xnew, float *z,
+                                  float *r32, double *partial, double *norm2, const GridArgs &g,
+                                  hipStream_t st);
 template <typename real>
 hipError_t launch_grid_fill(real *x, real v, const GridArgs &g, hipStream_t st);
 hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStream_t st);

@@ -139,88 +139,107 @@ __global__ void copy_shell_kernel(const real *__restrict__ a, real *__restrict__
 // r = (six neighbours of x, summed left to right) - 6x on the interior, FP64,
 // i.e. b - A x for A = 6I - adjacency with the shell of x as Dirichlet data.
 // Writes (float)r to r32 (interior) and a per-block partial sum of r^2.
-// Same strip structure as the plain sweep (PLAIN_ROWS rows x 512 cells per
-// block, k streamed with the strip's k-1, k, k+1 rows in registers); each
-// thread sums its cells' r^2 in stream order, the block sums its threads with
-// a fixed tree, so the result is the same run to run.
+// A block owns RB rows of 256 consecutive cells (one per thread) and streams
+// a k chunk with the strip's k-1, k, k+1 rows in registers; each thread sums
+// its cells' r^2 in stream order, the block sums its threads with a fixed
+// tree, so the result is the same run to run.
+//
+// FUSED: the refinement's update comes first.  The grid the residual is taken
+// of is xn = x + (double)e on the interior and x on the shell, formed on the
+// fly at every stencil point; the kernel writes xn to xnew, the residual of
+// xn, and zeroes the interior of z (the next inner solve's starting guess).
+// x, e, xnew and z are distinct buffers, so no thread reads what another
+// writes.
+template <int RB, bool FUSED>
 __global__ __launch_bounds__(256) void residual_kernel(const double *__restrict__ X,
+                                                       const float *__restrict__ E,
+                                                       double *__restrict__ xnew,
+                                                       float *__restrict__ z,
                                                        float *__restrict__ r32,
                                                        double *__restrict__ partial, PlainArgs p)
 {
-    constexpr int RB = PLAIN_ROWS;
     __shared__ double red[256];
-    const int i0 = 1 + blockIdx.x * 512 + 2 * threadIdx.x;
+    // one cell per thread: 256 consecutive cells of RB rows, streamed in k
+    const int i = 1 + blockIdx.x * 256 + threadIdx.x;
     const int j0 = 1 + blockIdx.y * RB;
     const int k0 = 1 + blockIdx.z * p.kchunk;
     const int k1 = min(k0 + p.kchunk, p.nz + 1);
-    const int ia = min(i0, p.nx + 1), ib = min(i0 + 1, p.nx + 1);
-    const int iw = min(i0 - 1, p.nx + 1), ie = min(i0 + 2, p.nx + 1);
+    const int ic = min(i, p.nx + 1), iw = min(i - 1, p.nx + 1), ie = min(i + 1, p.nx + 1);
+    // interior masks of the three i positions (FUSED only)
+    const bool mc = ic <= p.nx, mw = iw >= 1 && iw <= p.nx, me = ie <= p.nx;
     int64_t ro[RB + 2];
+    bool mj[RB + 2];
 #pragma unroll
-    for (int r = 0; r < RB + 2; ++r)
-        ro[r] = (int64_t)min(j0 - 1 + r, p.ny + 1) * p.sy;
-    auto load = [&](int k, double(&c)[RB + 2][2], double(&w)[RB], double(&e)[RB]) {
-        const double *pl = X + (int64_t)min(k, p.nz + 1) * p.sz;
-#pragma unroll
-        for (int r = 0; r < RB + 2; ++r) {
-            c[r][0] = pl[ro[r] + ia];
-            c[r][1] = pl[ro[r] + ib];
-        }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            w[r] = pl[ro[r + 1] + iw];
-            e[r] = pl[ro[r + 1] + ie];
+    for (int r = 0; r < RB + 2; ++r) {
+        const int j = j0 - 1 + r;
+        ro[r] = (int64_t)min(j, p.ny + 1) * p.sy;
+        mj[r] = j >= 1 && j <= p.ny;
+    }
+    // both loads are unconditional (o is always inside the arrays), so they
+    // issue back to back; the mask only selects
+    auto value = [&](const double *xp, const float *ep, int64_t o, bool in) -> double {
+        const double v = xp[o];
+        if constexpr (FUSED) {
+            const double u = v + (double)ep[o];
+            return in ? u : v;
+        } else {
+            return v;
         }
     };
-    double prev[RB][2], cur[RB + 2][2], cw[RB], ce[RB], nxt[RB + 2][2], nw[RB], ne[RB];
+    // c: the RB+2 rows at i; w, e: the RB inner rows at i-1 and i+1
+    auto load = [&](int k, double(&c)[RB + 2], double(&w)[RB], double(&e)[RB]) {
+        const int kc = min(k, p.nz + 1);
+        const double *pl = X + (int64_t)kc * p.sz;
+        const float *el = E + (FUSED ? (int64_t)kc * p.sz : 0);
+        const bool mk = kc >= 1 && kc <= p.nz;
+#pragma unroll
+        for (int r = 0; r < RB + 2; ++r)
+            c[r] = value(pl, el, ro[r] + ic, mk && mj[r] && mc);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const bool m = mk && mj[r + 1];
+            w[r] = value(pl, el, ro[r + 1] + iw, m && mw);
+            e[r] = value(pl, el, ro[r + 1] + ie, m && me);
+        }
+    };
+    double prev[RB], cur[RB + 2], cw[RB], ce[RB], nxt[RB + 2], nw[RB], ne[RB];
     load(k0 - 1, nxt, nw, ne);
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        prev[r][0] = nxt[r + 1][0];
-        prev[r][1] = nxt[r + 1][1];
-    }
+    for (int r = 0; r < RB; ++r)
+        prev[r] = nxt[r + 1];
     load(k0, cur, cw, ce);
     double acc = 0.0;
     for (int k = k0; k < k1; ++k) {
         load(k + 1, nxt, nw, ne);
-        float *out = r32 + (int64_t)k * p.sz;
+        const int64_t po = (int64_t)k * p.sz;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            double s0 = cw[r] + cur[r + 1][1];
-            s0 = s0 + cur[r][0];
-            s0 = s0 + cur[r + 2][0];
-            s0 = s0 + prev[r][0];
-            s0 = s0 + nxt[r + 1][0];
-            double s1 = cur[r + 1][0] + ce[r];
-            s1 = s1 + cur[r][1];
-            s1 = s1 + cur[r + 2][1];
-            s1 = s1 + prev[r][1];
-            s1 = s1 + nxt[r + 1][1];
-            const double six0 = 6.0 * cur[r + 1][0], six1 = 6.0 * cur[r + 1][1];
-            const double v0 = s0 - six0, v1 = s1 - six1;
-            if (j0 + r <= p.ny) {
-                if (i0 <= p.nx) {
-                    out[ro[r + 1] + i0] = (float)v0;
-                    acc = acc + v0 * v0;
-                }
-                if (i0 + 1 <= p.nx) {
-                    out[ro[r + 1] + i0 + 1] = (float)v1;
-                    acc = acc + v1 * v1;
+            double s = cw[r] + ce[r];
+            s = s + cur[r];
+            s = s + cur[r + 2];
+            s = s + prev[r];
+            s = s + nxt[r + 1];
+            const double six = 6.0 * cur[r + 1];
+            const double v = s - six;
+            if (j0 + r <= p.ny && i <= p.nx) {
+                const int64_t o = po + ro[r + 1] + i;
+                r32[o] = (float)v;
+                acc = acc + v * v;
+                if constexpr (FUSED) {
+                    xnew[o] = cur[r + 1];
+                    z[o] = 0.0f;
                 }
             }
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            prev[r][0] = cur[r + 1][0];
-            prev[r][1] = cur[r + 1][1];
+            prev[r] = cur[r + 1];
             cw[r] = nw[r];
             ce[r] = ne[r];
         }
 #pragma unroll
-        for (int r = 0; r < RB + 2; ++r) {
-            cur[r][0] = nxt[r][0];
-            cur[r][1] = nxt[r][1];
-        }
+        for (int r = 0; r < RB + 2; ++r)
+            cur[r] = nxt[r];
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -543,32 +562,54 @@ static dim3 strip_grid(const GridArgs &g)
                 (unsigned)((g.nz + RES_KC - 1) / RES_KC));
 }
 
-// Residual geometry: row strips like the plain sweep, k chunks of RES_KCHUNK
+// Residual geometry: RB-row strips of 256 cells (RES_RB rows for the
+// residual alone, FUSED_RB for the fused form, which loads twice as much per
+// row), k chunks of RES_KCHUNK.  The partial sums are sized for the larger
+// of the two grids.
 static constexpr int RES_KCHUNK = 64;
-static dim3 residual_grid(const GridArgs &g)
+static constexpr int RES_RB = 8;
+static constexpr int FUSED_RB = 4;
+static dim3 residual_grid(const GridArgs &g, int rb)
 {
-    return dim3((unsigned)((g.nx + 511) / 512), (unsigned)((g.ny + PLAIN_ROWS - 1) / PLAIN_ROWS),
+    return dim3((unsigned)((g.nx + 255) / 256), (unsigned)((g.ny + rb - 1) / rb),
                 (unsigned)((g.nz + RES_KCHUNK - 1) / RES_KCHUNK));
 }
 
 int64_t residual_partials(const GridArgs &g)
 {
-    const dim3 d = residual_grid(g);
+    const dim3 d = residual_grid(g, FUSED_RB);  // the larger of the two grids
     return (int64_t)d.x * d.y * d.z;
+}
+
+static hipError_t sum_partials(const double *partial, const dim3 &grid, double *norm2,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, partial,
+                       (int64_t)grid.x * grid.y * grid.z, norm2);
+    return hipGetLastError();
 }
 
 hipError_t launch_residual(const double *x, float *r32, double *partial, double *norm2,
                            const GridArgs &g, hipStream_t st)
 {
-    const dim3 grid = residual_grid(g);
+    const dim3 grid = residual_grid(g, RES_RB);
     PlainArgs p{(int)g.nx, (int)g.ny, (int)g.nz, RES_KCHUNK, g.sy, g.sz};
-    hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, st, x, r32, partial, p);
+    hipLaunchKernelGGL((residual_kernel<RES_RB, false>), grid, dim3(256), 0, st, x, nullptr,
+                       nullptr, nullptr, r32, partial, p);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, partial,
-                       residual_partials(g), norm2);
-    return hipGetLastError();
+    return e != hipSuccess ? e : sum_partials(partial, grid, norm2, st);
+}
+
+hipError_t launch_update_residual(const double *x, const float *e32, double *xnew, float *z,
+                                  float *r32, double *partial, double *norm2, const GridArgs &g,
+                                  hipStream_t st)
+{
+    const dim3 grid = residual_grid(g, FUSED_RB);
+    PlainArgs p{(int)g.nx, (int)g.ny, (int)g.nz, RES_KCHUNK, g.sy, g.sz};
+    hipLaunchKernelGGL((residual_kernel<FUSED_RB, true>), grid, dim3(256), 0, st, x, e32, xnew, z,
+                       r32, partial, p);
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : sum_partials(partial, grid, norm2, st);
 }
 
 hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStream_t st)

@@ -483,29 +483,32 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
         const int tk = m.tile / (G.nti * G.ntj);
         int *cnt = L.counters + 1 + G.counter_off;
         if (L.persistent && m.pass > 0) {
-            if (threadIdx.x == 0) {
-                for (int dk = -1; dk <= 1; ++dk)
-                    for (int dj = -1; dj <= 1; ++dj)
-                        for (int di = -1; di <= 1; ++di) {
-                            const int a = ti + di, b = tj + dj, c = tk + dk;
-                            if (a < 0 || a >= G.nti || b < 0 || b >= G.ntj || c < 0 || c >= G.nkc)
-                                continue;
-                            const int *q = cnt + (c * G.ntj + b) * G.nti + a;
-                            // bounded wait (seconds): a wait that cannot end
-                            // raises the error flag instead of hanging
-                            int spins = 0;
-                            while (__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                                   m.pass) {
-                                __builtin_amdgcn_s_sleep(2);
-                                if (++spins > L.spin_limit ||
-                                    __hip_atomic_load(L.error, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT)) {
-                                    __hip_atomic_store(L.error, 1, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                                    break;
-                                }
-                            }
-                        }
+            // wave 0 polls the 27 neighbour counters at once, lane n the block
+            // at offset (n % 3, n / 3 % 3, n / 9) - 1, until every lane sees
+            // its condition hold
+            if (threadIdx.x < 64) {
+                const int n = threadIdx.x;
+                const int a = ti + n % 3 - 1, b = tj + n / 3 % 3 - 1, c = tk + n / 9 - 1;
+                const bool mine = n < 27 && a >= 0 && a < G.nti && b >= 0 && b < G.ntj && c >= 0 &&
+                                  c < G.nkc;
+                const int *q = cnt + (mine ? (c * G.ntj + b) * G.nti + a : 0);
+                // bounded wait (seconds): a wait that cannot end raises the
+                // error flag instead of hanging; every decision is wave-uniform
+                int spins = 0;
+                for (;;) {
+                    const bool ok =
+                        !mine || __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= m.pass;
+                    if (__all(ok))
+                        break;
+                    __builtin_amdgcn_s_sleep(2);
+                    const int err = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(L.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (++spins > L.spin_limit || err) {
+                        if (n == 0)
+                            __hip_atomic_store(L.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                }
             }
             __syncthreads();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

@@ -177,6 +177,26 @@ def update_f64(x, e32):
     return x
 
 
+def update_residual_f64(x, e32, x_new, r32, zero32, norm2, ws=None):
+    """x_new <- x + (double)e32 and zero32 <- 0 on the interior; r32 and
+    norm2 as residual_f64 gives them for x_new.  All six tensors distinct."""
+    if (x.dtype != torch.float64 or x_new.dtype != torch.float64 or norm2.dtype != torch.float64
+            or e32.dtype != torch.float32 or r32.dtype != torch.float32
+            or zero32.dtype != torch.float32):
+        raise TypeError("update_residual_f64 needs float64 x, x_new, norm2 and float32 e32, r32, "
+                        "zero32")
+    for other in (e32, x_new, r32, zero32):
+        if other.shape != x.shape or other.stride() != x.stride():
+            raise ValueError("the grids must share shape and strides")
+    if ws is None:
+        ws = residual_workspace(x)
+    with torch.cuda.device(x.device):
+        check(_lib.load().jacobi_update_residual_f64(
+            ctypes.byref(grid_of(x)), _ptr(x), _ptr(e32), _ptr(x_new), _ptr(r32), _ptr(zero32),
+            _ptr(norm2), _ptr(ws), ws.numel(), _stream(x)))
+    return x_new
+
+
 class BatchPlan:
     """A batched run over independent grids (one blocking choice for all).
 

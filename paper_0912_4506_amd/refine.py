@@ -20,26 +20,33 @@ from . import jacobi
 
 
 def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, callback=None,
-                 bx=0, by=0, waves=0):
+                 bx=0, by=0, waves=0, fused=True):
     """Solve in place.  x: float64 GPU grid (shell = Dirichlet data, interior
     = initial guess).  Returns (x, outer_iterations, relative_residual).
     ``check_every`` > 1 reads the norm only every that many outer iterations
     (fewer host synchronisations; the stopping point is then a multiple).
     t, bx, by, waves: blocking of the inner FP32 sweeps (t=None and 0: the
-    library's choice)."""
+    library's choice).  ``fused``: update x and take the next residual in
+    one pass over memory (x then alternates between two buffers, and the
+    next inner solve's zero guess is written in the same pass); False runs
+    the update, the residual and the zero fill as separate kernels.  Both
+    give bitwise the same iterates."""
     if x.dtype != torch.float64:
         raise TypeError("x must be float64")
     r32 = torch.empty(x.shape, dtype=torch.float32, device=x.device)
     jacobi.fill(r32, 0.0)
     e_a = torch.empty_like(r32)
     e_b = torch.empty_like(r32)
+    jacobi.fill(e_a, 0.0)
+    jacobi.fill(e_b, 0.0)
     norm2 = torch.zeros(1, dtype=torch.float64, device=x.device)
     ws = jacobi.residual_workspace(x)
+    xa, xb = x, (x.clone() if fused else None)
+    jacobi.residual_f64(xa, r32, norm2, ws)
     r0 = None
     rel = float("inf")
     it = 0
     while True:
-        jacobi.residual_f64(x, r32, norm2, ws)
         if it % check_every == 0 or it >= max_outer:
             n = math.sqrt(norm2.item())
             if r0 is None:
@@ -49,10 +56,20 @@ def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, ca
                 callback(it, rel)
             if rel <= tol or it >= max_outer:
                 break
-        jacobi.fill(e_a, 0.0)
+        # e_a holds zeros (interior and shell); e_b is scratch with a zero shell
         e = jacobi.tblock(e_a, e_b, inner, t=t, bx=bx, by=by, waves=waves, rhs=r32)
-        jacobi.update_f64(x, e)
+        other = e_b if e is e_a else e_a
+        if fused:
+            jacobi.update_residual_f64(xa, e, xb, r32, other, norm2, ws)
+            xa, xb = xb, xa
+        else:
+            jacobi.update_f64(xa, e)
+            jacobi.residual_f64(xa, r32, norm2, ws)
+            jacobi.fill(other, 0.0)
+        e_a, e_b = other, e
         it += 1
+    if xa is not x:
+        x.copy_(xa)
     return x, it, rel
 
 

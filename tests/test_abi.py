@@ -114,5 +114,20 @@ def test_residual_and_copy_checks(lib):
     assert lib.jacobi_residual_f64(ctypes.byref(g), A, B, n2, None, 0, None) == JAC_EWORKSPACE
     assert lib.jacobi_residual_f64(ctypes.byref(g), A, P((1 << 20) + 16), n2, P(1 << 38), need,
                                    None) == JAC_EARG
+    # the fused update-residual: missing workspace, then overlapping buffers
+    bufs = [P(1 << k) for k in (20, 22, 24, 26, 28)]   # x, e32, x_new, r32, zero32
+    assert lib.jacobi_update_residual_f64(ctypes.byref(g), *bufs, n2, None, 0,
+                                          None) == JAC_EWORKSPACE
+    assert lib.jacobi_update_residual_f64(ctypes.byref(g), *bufs, n2, P(1 << 38), need - 8,
+                                          None) == JAC_EWORKSPACE
+    for u in range(5):
+        bad = list(bufs)
+        bad[u] = P(bufs[(u + 1) % 5].value + 64)       # inside the next buffer
+        assert lib.jacobi_update_residual_f64(ctypes.byref(g), *bad, n2, P(1 << 38), need,
+                                              None) == JAC_EARG, u
+        assert "overlap" in err(lib)
+    assert lib.jacobi_update_residual_f64(ctypes.byref(g), bufs[0], bufs[1], bufs[2], bufs[3],
+                                          bufs[4], P(bufs[3].value + 8), P(1 << 38), need,
+                                          None) == JAC_EARG             # norm2 inside r32
     assert lib.jacobi_copy(A, P((1 << 20) + 16), 64, None) == JAC_EARG   # overlap
     assert lib.jacobi_copy(A, B, 12, None) == JAC_EARG                   # not a multiple of 16

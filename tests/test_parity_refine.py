@@ -51,6 +51,60 @@ def test_update_and_fill(jac):
     assert torch.count_nonzero(et).item() == 0
 
 
+@pytest.mark.parametrize("shape", [(30, 17, 23), (530, 19, 70), (1, 1, 1)])
+def test_update_residual_fused(jac, shape):
+    """x_new = x + e bitwise, the residual of x_new bitwise before the cast
+    (its norm to 1e-12), zero32's interior zeroed, and every shell untouched;
+    equal to the separate update and residual kernels."""
+    nx, ny, nz = shape
+    x = inputs.grid(nx, ny, nz, seed=11)
+    e = inputs.grid(nx, ny, nz, seed=12, dtype=np.float32) - np.float32(0.5)
+    e[0, :, :] = e[-1, :, :] = 0
+    e[:, 0, :] = e[:, -1, :] = 0
+    e[:, :, 0] = e[:, :, -1] = 0
+    want_x = x.copy()
+    want_x[1:-1, 1:-1, 1:-1] += e[1:-1, 1:-1, 1:-1].astype(np.float64)
+    r_ref, n2_ref = oracle.residual(want_x)
+    xt, et = dev(x), dev(e, torch.float32)
+    xn = torch.full_like(xt, float("nan"))
+    xn[0], xn[-1], xn[:, 0], xn[:, -1], xn[:, :, 0], xn[:, :, -1] = (
+        xt[0], xt[-1], xt[:, 0], xt[:, -1], xt[:, :, 0], xt[:, :, -1])
+    r32 = torch.full(xt.shape, 7.0, dtype=torch.float32, device="cuda")
+    z = torch.full(xt.shape, 3.0, dtype=torch.float32, device="cuda")
+    norm2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    jac.update_residual_f64(xt, et, xn, r32, z, norm2)
+    torch.cuda.synchronize()
+    assert np.array_equal(xn.cpu().numpy(), want_x)
+    got_r = r32.cpu().numpy()
+    assert np.array_equal(got_r[1:-1, 1:-1, 1:-1], r_ref[1:-1, 1:-1, 1:-1].astype(np.float32))
+    shell = np.ones(x.shape, bool)
+    shell[1:-1, 1:-1, 1:-1] = False
+    assert np.all(got_r[shell] == 7.0)
+    zz = z.cpu().numpy()
+    assert np.all(zz[1:-1, 1:-1, 1:-1] == 0.0) and np.all(zz[shell] == 3.0)
+    assert math.isclose(norm2.item(), n2_ref, rel_tol=1e-12)
+    assert np.array_equal(xt.cpu().numpy(), x)              # the input is left alone
+    # the separate kernels give the same grid and residual
+    x2 = dev(x)
+    r2 = torch.zeros_like(r32)
+    n2b = torch.zeros_like(norm2)
+    jac.update_f64(x2, et)
+    jac.residual_f64(x2, r2, n2b)
+    assert torch.equal(x2, xn)
+    assert torch.equal(r2[1:-1, 1:-1, 1:-1], r32[1:-1, 1:-1, 1:-1])
+
+
+def test_refine_fused_equals_separate(jac):
+    """The fused and the separate outer steps produce bitwise the same
+    iterates and stop after the same number of outer iterations."""
+    from paper_0912_4506_amd.refine import refine_solve
+    g = inputs.laplace_problem(40, 33, 29, seed=3)
+    xf, of, rf = refine_solve(dev(g), tol=1e-9, inner=50, t=5, fused=True)
+    xs, os_, rs = refine_solve(dev(g), tol=1e-9, inner=50, t=5, fused=False)
+    assert of == os_ and rf == rs
+    assert torch.equal(xf, xs)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_fill_dense_and_strided(jac, dtype):
     # dense grids take the flat path (odd element count: a ragged tail);
@@ -65,7 +119,9 @@ def test_fill_dense_and_strided(jac, dtype):
     assert torch.all(base[:, :, 7:] == 1.0).item()
 
 
-@pytest.mark.parametrize("dtype,t", [(torch.float64, 4), (torch.float64, 8), (torch.float32, 8)])
+@pytest.mark.parametrize("dtype,t", [(torch.float64, 4), (torch.float64, 8), (torch.float32, 4),
+                                     (torch.float32, 5), (torch.float32, 6), (torch.float32, 7),
+                                     (torch.float32, 8)])
 def test_rhs_sweeps(jac, dtype, t):
     """jacobi_tblock with rhs from e = 0: FP64 bitwise with the oracle's
     right-hand-side sweeps; FP32 within 1e-5 of max|e|."""
@@ -82,6 +138,27 @@ def test_rhs_sweeps(jac, dtype, t):
         assert np.array_equal(got, ref)
     else:
         assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_rhs_sweeps_every_shape(jac, dtype):
+    """Every compiled block shape with a right-hand side at depth 5 (FP64:
+    bitwise; FP32: within 1e-5 of max|e|), on a grid that spans several
+    blocks in i and j with ragged tails."""
+    nx, ny, nz, T = 140, 97, 21, 12
+    r = inputs.grid(nx, ny, nz, seed=10)
+    np_dt = np.float64 if dtype == torch.float64 else np.float32
+    r = r.astype(np_dt)
+    ref = oracle.rhs_sweeps(r.astype(np.float64), T)
+    for bx, by, w in jac.tile_menu(dtype):
+        a = torch.zeros(r.shape, dtype=dtype, device="cuda")
+        b = torch.full_like(a, float("nan"))
+        out = jac.tblock(a, b, T, t=5, bx=bx, by=by, waves=w, rhs=dev(r, dtype))
+        got = out.cpu().numpy().astype(np.float64)
+        if dtype == torch.float64:
+            assert np.array_equal(got, ref), (bx, by, w)
+        else:
+            assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref)), (bx, by, w)
 
 
 @pytest.mark.parametrize("n", [16, 24])
