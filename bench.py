@@ -358,7 +358,7 @@ def main():
     ap.add_argument("--bx", type=int, default=0, help="pin the block shape (with --t)")
     ap.add_argument("--by", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
-    ap.add_argument("--depths", default="1,2,3,4,5,6",
+    ap.add_argument("--depths", default="1,2,3,4,5,6,8",
                     help="depths reported in by_depth (best block shape each)")
     ap.add_argument("--traffic", default=None,
                     help="measured HBM GB per blocked launch to report as roofline.traffic")
