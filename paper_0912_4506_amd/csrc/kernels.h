@@ -24,7 +24,8 @@
 
 namespace jac {
 
-enum { MODE_PLAIN = 0, MODE_RHS = 1, MODE_TRACE = 2 };
+// MODE_BATCH is MODE_PLAIN with agent-scope output stores (see batched_kernel)
+enum { MODE_PLAIN = 0, MODE_RHS = 1, MODE_TRACE = 2, MODE_BATCH = 3 };
 enum { FACES_SAVE = 0, FACES_ZERO = 1, FACES_CLEAR_SUM = 2, FACES_ACCUM = 3, FACES_FINALIZE = 4 };
 
 struct GridArgs {

@@ -339,8 +339,13 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                         real *row = dplane + rowoff[r];
 #pragma unroll
                         for (int c = 0; c < CI; ++c)
-                            if (ok_i[c])
-                                row[ic[c]] = o[r][c];
+                            if (ok_i[c]) {
+                                if constexpr (MODE == MODE_BATCH)
+                                    __hip_atomic_store(&row[ic[c]], o[r][c], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                                else
+                                    row[ic[c]] = o[r][c];
+                            }
                     }
             }
             // advance P[s-1] (rows 1 .. R-2) from the plane delivered to level s
@@ -530,11 +535,16 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
         p.kchunk = G.kchunk;
         const int depth = G.T / G.passes + (m.pass < G.T % G.passes ? 1 : 0);
         const int k0 = 1 + tk * G.kchunk;
-        tb_tile<real, TL, CI, R, W, MODE_PLAIN>(p, ti, tj, k0, min(k0 + G.kchunk, G.nz + 1), depth,
+        tb_tile<real, TL, CI, R, W, MODE_BATCH>(p, ti, tj, k0, min(k0 + G.kchunk, G.nz + 1), depth,
                                                 xch);
         if (!L.persistent)
             break;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // Publish: the item's output stores are agent-scope, so they write
+        // through this XCD's L2; once every wave has seen them complete
+        // (vmcnt 0) they are visible to all XCDs, which an agent-scope release
+        // fence would otherwise ensure by writing back the whole L2.  The
+        // consumer's acquire fence invalidates its own stale lines.
+        __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
         __syncthreads();
         if (threadIdx.x == 0)
             __hip_atomic_store(cnt + m.tile, m.pass + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
