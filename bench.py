@@ -32,8 +32,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# (t, bx, by) -> measured HBM GB per launch of the blocked kernel at 512^3 FP64
-MEASURED_TRAFFIC_GB = {(4, 64, 48, 8): 2.533}
+# (t, bx, by, waves) -> measured HBM GB per launch of the blocked kernel at
+# 512^3 FP64 (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales the
+# 2 GiB copy gives; profiles/tblock_f64_t4_64x56_512cubed.md)
+MEASURED_TRAFFIC_GB = {(4, 64, 56, 8): 2.366}
 METRIC = "GLUP/s & % roofline, 512³ FP64 Jacobi T=100: temporal-blocked vs plain"
 
 
