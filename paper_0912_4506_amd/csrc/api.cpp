@@ -253,7 +253,7 @@ int default_depth(int dtype, int kind)
 {
     if (dtype == JAC_F64)
         return kind == KIND_BATCH ? 5 : 4;
-    return kind == KIND_RHS ? 5 : 6;
+    return kind == KIND_TRACE ? 6 : 5;
 }
 
 // Per-lane scratch bytes (register spills) of the kernel a choice selects;
@@ -268,19 +268,19 @@ int kind_scratch(int dtype, int kind, int cfg, int depth)
 }
 
 // Block shapes measured fastest on MI355X at a given depth: 512^3 sweeps
-// without a right-hand side (T = 100) and 768^3 FP32 sweeps with one (T = 50).
-// Some of these spill a few registers and are still the fastest.
+// without a right-hand side (T = 100; FP64 depth 5 also at 768^3, where it is
+// the best depth) and 768^3 FP32 sweeps with one (T = 50).
 struct MeasuredShape {
     int dtype, kind, t, bx, by, waves;
 };
 const MeasuredShape kMeasured[] = {
-    {JAC_F64, KIND_PLAIN, 3, 64, 64, 8},  {JAC_F64, KIND_PLAIN, 4, 64, 56, 8},
-    {JAC_F64, KIND_PLAIN, 5, 64, 32, 8},  {JAC_F64, KIND_PLAIN, 6, 64, 32, 8},
-    {JAC_F32, KIND_PLAIN, 4, 64, 64, 16}, {JAC_F32, KIND_PLAIN, 5, 64, 64, 16},
-    {JAC_F32, KIND_PLAIN, 6, 64, 64, 16}, {JAC_F32, KIND_PLAIN, 7, 64, 64, 8},
-    {JAC_F32, KIND_PLAIN, 8, 64, 48, 16}, {JAC_F32, KIND_RHS, 4, 64, 56, 8},
-    {JAC_F32, KIND_RHS, 5, 64, 64, 16},   {JAC_F32, KIND_RHS, 6, 64, 48, 16},
-    {JAC_F32, KIND_RHS, 7, 64, 48, 8},    {JAC_F32, KIND_RHS, 8, 64, 48, 8},
+    {JAC_F64, KIND_PLAIN, 3, 64, 64, 8},  {JAC_F64, KIND_PLAIN, 4, 64, 60, 12},
+    {JAC_F64, KIND_PLAIN, 5, 64, 56, 8},  {JAC_F64, KIND_PLAIN, 6, 64, 48, 8},
+    {JAC_F32, KIND_PLAIN, 4, 64, 60, 12}, {JAC_F32, KIND_PLAIN, 5, 64, 64, 16},
+    {JAC_F32, KIND_PLAIN, 6, 64, 80, 16}, {JAC_F32, KIND_PLAIN, 7, 64, 80, 16},
+    {JAC_F32, KIND_PLAIN, 8, 64, 80, 16}, {JAC_F32, KIND_RHS, 4, 64, 80, 16},
+    {JAC_F32, KIND_RHS, 5, 64, 80, 16},   {JAC_F32, KIND_RHS, 6, 64, 64, 16},
+    {JAC_F32, KIND_RHS, 7, 64, 64, 16},   {JAC_F32, KIND_RHS, 8, 64, 64, 16},
 };
 
 // Untuned default block shape: the measured one for (dtype, kind, t) if there

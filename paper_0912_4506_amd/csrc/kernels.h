@@ -20,7 +20,9 @@
     X(6, 1, 3, 16)       \
     X(7, 1, 4, 16)       \
     X(8, 2, 2, 16)       \
-    X(9, 1, 7, 8)
+    X(9, 1, 7, 8)        \
+    X(10, 1, 5, 12)      \
+    X(11, 1, 5, 16)
 
 namespace jac {
 

@@ -83,9 +83,11 @@ constexpr size_t xch_bytes()
 // (P + U) / 6 -- the full left-to-right sum -- with no neighbour exchange, so
 // the levels run back to back.  Then the newly delivered planes of all levels
 // are exchanged at once (i-neighbours by DPP wave shifts, j-neighbours from
-// registers, and across wave boundaries through LDS) and P, Q advance.  The
-// stream loop is unrolled twice with the two Q sets swapping roles, so no
-// register copies carry Q from one step to the next.
+// registers, and across wave boundaries through LDS) and P, Q advance.
+// Q is carried from one step to the next by copying the new set back after
+// every step: one move per value.  (Unrolling the loop twice with the two
+// sets swapping roles needs no copies, but the compiler then keeps about 50
+// more VGPRs live, and the register budget is what limits the block.)
 // Loads clamp their coordinates into the array: cells outside it hold
 // garbage that only ever reaches other outside cells or shell cells, and
 // shell cells (i, j or k = 0 or n+1) pass their value through at every level.
@@ -103,7 +105,7 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
     const AxisTile xi = axis_tile(ti, p.nx, 64 * CI, p.hi);
     const AxisTile xj = axis_tile(tj, p.ny, W * R, TL);
     const int kstart = max(k0 - depth, 0);
-    const int nsteps = ((k1 - 1 + depth) - kstart + 2) & ~1;  // rounded up to even
+    const int nsteps = (k1 + depth) - kstart;  // steps kstart .. k1-1+depth
 
     // per-lane columns
     int ic[CI];
@@ -423,9 +425,20 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
         }
     };
 
-    for (int n = 0; n < nsteps; n += 2) {
+    for (int n = 0; n < nsteps; ++n) {
         step(kstart + n, QA, QB, CA, CB);
-        step(kstart + n + 1, QB, QA, CB, CA);
+#pragma unroll
+        for (int s = 0; s < TL; ++s)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < CI; ++c)
+                    QA[s][r][c] = QB[s][r][c];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < CI; ++c)
+                CA[r][c] = CB[r][c];
     }
 }
 
