@@ -34,8 +34,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # (t, bx, by, waves) -> measured HBM GB per launch of the blocked kernel at
 # 512^3 FP64 (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales the
-# 2 GiB copy gives; profiles/tblock_f64_t4_64x60_512cubed.md)
-MEASURED_TRAFFIC_GB = {(4, 64, 60, 12): 2.407}
+# 2 GiB copy gives; profiles/tblock_f64_t4_64x72_512cubed.md)
+MEASURED_TRAFFIC_GB = {(4, 64, 72, 12): 2.337}
 METRIC = "GLUP/s & % roofline, 512³ FP64 Jacobi T=100: temporal-blocked vs plain"
 
 

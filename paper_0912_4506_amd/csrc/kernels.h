@@ -22,7 +22,8 @@
     X(8, 2, 2, 16)       \
     X(9, 1, 7, 8)        \
     X(10, 1, 5, 12)      \
-    X(11, 1, 5, 16)
+    X(11, 1, 5, 16)      \
+    X(12, 1, 6, 12)
 
 namespace jac {
 

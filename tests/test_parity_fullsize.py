@@ -34,16 +34,17 @@ def samples():
     """(i, j, k) array indices of the sampled cells."""
     rng = np.random.default_rng(123)
     pts = {(1, 1, 1), (N, N, N), (1, N, 1), (N, 1, N), (N // 2, N // 2, N // 2)}
-    # block edges of the default 64 x 56 plan at depth 4: valid i ranges start
-    # at 1, 60, 116, ..., 508 and j ranges at 1, 52, 100, ..., 484; k chunks
-    # meet at 257
+    # block edges at depth 4: 64-lane blocks start their valid i ranges at 1,
+    # 60, 116, ..., 508; 72-row blocks (the default) their j ranges at 1, 68,
+    # 132, ..., 452, and 56-row blocks at 1, 52, 100, ..., 484; k chunks of
+    # 2, 3 or 5 per column meet near 257, 172 / 343 and 103 / 206 / ...
     for i in (59, 60, 115, 116, 507, 508):
         pts.add((i, int(rng.integers(1, N + 1)), int(rng.integers(1, N + 1))))
-    for j in (51, 52, 99, 100, 483, 484):
+    for j in (67, 68, 131, 132, 451, 452, 51, 52, 483, 484):
         pts.add((int(rng.integers(1, N + 1)), j, int(rng.integers(1, N + 1))))
-    for k in (256, 257, 2, N - 1):
+    for k in (256, 257, 171, 172, 342, 343, 103, 104, 2, N - 1):
         pts.add((int(rng.integers(1, N + 1)), int(rng.integers(1, N + 1)), k))
-    while len(pts) < 40:
+    while len(pts) < 48:
         pts.add(tuple(int(x) for x in rng.integers(1, N + 1, size=3)))
     return sorted(pts)
 
