@@ -88,10 +88,18 @@ def cpu_baseline(u, T, lups_per_sweep, target_s=12.0):
     t0 = time.perf_counter()
     oracle.sweeps(u, sweeps)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread: one sweep's time, as the difference of a
+    # two-sweep and a one-sweep run (allocation and first touch cancel)
+    t1 = time.perf_counter()
+    oracle.sweeps(u, 2, nthreads=1)
+    t2 = time.perf_counter()
+    oracle.sweeps(u, 1, nthreads=1)
+    dt1 = max((t2 - t1) - (time.perf_counter() - t2), 1e-6)
     n = round(u.shape[0] - 2)
     return {"value": round(lups_per_sweep * sweeps / dt / 1e9, 4), "unit": "GLUP/s",
             "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{n}^3 FP64 grid, {sweeps} of the {T} sweeps, one run ({dt:.1f} s)"}
+            "sample": f"{n}^3 FP64 grid, {sweeps} of the {T} sweeps, one run ({dt:.1f} s)",
+            "single_thread": round(lups_per_sweep / dt1 / 1e9, 4)}
 
 
 def bench_metric(args):
