@@ -18,7 +18,8 @@ of the next; the work does not depend on the values).
 Other workloads (--workload): `batched` (64 grids, edges log-uniform in
 [32, 256], T = 50, one persistent launch), `adjoint` (256^3, T = 32, t = 8,
 forward + backward), `refine` (768^3 Laplace solve, FP32 inner / FP64 outer,
-vs all-FP64 Jacobi; runs many minutes).
+vs all-FP64 Jacobi; runs many minutes), `pipelined` (512^3, T = 100, by the
+pipelined schedule).
 """
 import argparse
 import json
@@ -286,6 +287,47 @@ def bench_adjoint(args):
     return out
 
 
+def bench_pipelined(args):
+    """512^3 FP64, T = 100 by pipelined temporal blocking (the team pipeline
+    with relaxed synchronisation, one persistent launch): the fastest of a
+    small set of (team, sweeps per item, k chunk) against the overlapped-tile
+    default and the plain kernel on the same grid."""
+    import torch
+    from paper_0912_4506_amd import inputs, jacobi as jac
+
+    N, T = 512, 100
+    u = inputs.grid(N, N, N, seed=0)
+    a = torch.from_numpy(u).to("cuda")
+    b = torch.empty_like(a)
+    lups = N ** 3 * T
+    rows = []
+    for team in (1, 2, 4, 8):
+        for t in (1, 2, 4):
+            for kc in (16, 32, 64, 128):
+                try:
+                    plan = jac.PipelinePlan(a, b, T, team=team, t=t, kchunk=kc)
+                except Exception as e:          # a refused shape: skip it
+                    print(f"  team {team} t {t} kchunk {kc}: {e}", file=sys.stderr)
+                    continue
+                ms = time_steps(lambda: plan.run("relaxed"), max(1, args.steps // 2), 1)
+                if plan.wait_error():
+                    raise RuntimeError("a relaxed-mode wait gave up")
+                rows.append({"team": team, "t": t, "kchunk": kc,
+                             "glups": round(lups / (ms * 1e-3) / 1e9, 1)})
+                print(f"  team {team} t {t} kchunk {kc}: {rows[-1]['glups']} GLUP/s", file=sys.stderr,
+                      flush=True)
+                del plan
+    best = max(rows, key=lambda r: r["glups"])
+    bms = time_steps(lambda: jac.tblock(a, b, T), args.steps, 1)
+    pms = time_steps(lambda: jac.plain(a, b, T), max(1, args.steps // 2), 1)
+    return {"metric": "GLUP/s, 512^3 FP64 Jacobi T=100, pipelined temporal blocking", "unit": "GLUP/s",
+            "value": best["glups"], "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
+            "data": "synthetic: uniform [0,1) interior and shell, numpy default_rng(0)",
+            "config": {"workload": "jacobi3d 512^3 interior, FP64, T=100", **best},
+            "overlapped_tiles_glups": round(lups / (bms * 1e-3) / 1e9, 1),
+            "plain_glups": round(lups / (pms * 1e-3) / 1e9, 1), "candidates": rows}
+
+
 def bench_refine(args):
     """Laplace solve to a relative FP64 residual of 1e-10 from a zero interior:
     FP64 refinement around FP32 blocked inner sweeps (50 per outer iteration)
@@ -367,7 +409,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="metric",
-                    choices=["metric", "batched", "adjoint", "refine"])
+                    choices=["metric", "batched", "adjoint", "refine", "pipelined"])
     ap.add_argument("--autotune", action="store_true",
                     help="let the library's autotuner pick the blocking first")
     ap.add_argument("--tmax", type=int, default=8, help="deepest blocking depth the autotuner tries")
@@ -398,7 +440,7 @@ def main():
         sys.exit(2)
     ensure_built()
     fn = {"metric": bench_metric, "batched": bench_batched, "adjoint": bench_adjoint,
-          "refine": bench_refine}[args.workload]
+          "refine": bench_refine, "pipelined": bench_pipelined}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

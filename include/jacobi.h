@@ -171,6 +171,27 @@ size_t jacobi_batched_workspace(const void *plan_host);
 int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws,
                        size_t ws_bytes, int mode, void *stream);
 
+/* Pipelined temporal blocking of one grid: the team pipeline of Sect. 1.2 with
+ * the relaxed synchronisation of Sect. 1.3 (the lower bound of Eq. 3), in GPU
+ * form.  T sweeps are cut into passes of tile->t sweeps (t = 0: 1 sweep per
+ * item); each item runs one pass on one block of k chunk q (tile->kchunk
+ * planes, 0: 16) and waits for the 27 neighbouring blocks of the previous
+ * pass.  Consecutive passes form segments of `team` passes (1..1024); within
+ * a segment the items go out in wavefronts, pass p on chunk q beside pass p+1
+ * on chunk q-1, so the passes of a segment stream through the grid one chunk
+ * apart, as the threads of a team follow each other through the blocks of a
+ * shared cache.  No cell is computed more often than with tile->t sweeps per
+ * block (no halo is recomputed when t = 1).  The plan image has the layout of
+ * a one-grid batch: size it with jacobi_pipelined_plan_bytes, copy it to the
+ * device, size the workspace with jacobi_batched_workspace and run it with
+ * jacobi_batched_run in JAC_BATCH_RELAXED mode (lockstep is refused, JAC_EARG).
+ * a, b, out_idx_host and the errors are as for jacobi_batched_plan with n = 1. */
+size_t jacobi_pipelined_plan_bytes(int dtype, const jac_grid_t *g, int T,
+                                   const jac_tile_t *tile);
+int jacobi_pipelined_plan(int dtype, const jac_grid_t *g, void *a, void *b, int T,
+                          int team, const jac_tile_t *tile, void *plan_host,
+                          size_t plan_bytes, int *out_idx_host);
+
 /* Mixed-precision refinement helpers (outer FP64 loop around an FP32 Jacobi
  * inner solve; the refinement is not in the paper, the operator is the
  * Laplace system whose fixed point the Jacobi iteration of Sect. 1.1 seeks).

@@ -468,6 +468,10 @@ int run_adjoint(const Geo &g, real *la, real *lb, int T, const jac_tile_t &tile,
 }
 
 // ---------------------------------------------------------- batched plans --
+// Default k chunk (planes per item) of a pipelined plan: short slabs, so that
+// the passes in flight work on data the caches still hold.
+constexpr int PIPELINE_KCHUNK = 16;
+
 size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 struct BatchSizes {
@@ -832,11 +836,19 @@ size_t jacobi_batched_plan_bytes(int dtype, int n, const jac_grid_t *g, const in
     return batch_image_bytes(n, z);
 }
 
-int jacobi_batched_plan(int dtype, int n, const jac_grid_t *g, void *const *a, void *const *b,
-                        const int *T, const jac_tile_t *tile, void *plan_host, size_t plan_bytes,
-                        int *out_idx_host)
+// Plan image of a batched run.  team = 0: items pass by pass.  team >= 1
+// (one grid): the pipelined schedule of temporal blocking (Sect. 1.2, 1.3)
+// in GPU form.  The passes form segments of `team` consecutive passes; within
+// a segment, wavefront w holds pass seg + s on k chunk w - s for every s, so
+// pass p works on the chunk just behind the one pass p-1 works on, like the
+// threads of a team following each other through the blocks of a shared
+// cache.  Every item's neighbours of the previous pass come earlier in this
+// order (same or earlier wavefront, earlier pass), which keeps the relaxed
+// waits deadlock-free.
+static int build_plan(int dtype, int n, const jac_grid_t *g, void *const *a, void *const *b,
+                      const int *T, const jac_tile_t *tile, void *plan_host, size_t plan_bytes,
+                      int *out_idx_host, int team)
 {
-    g_err.clear();
     jac_tile_t tl;
     GridPlan *plans = nullptr;
     BatchSizes z;
@@ -876,6 +888,8 @@ int jacobi_batched_plan(int dtype, int n, const jac_grid_t *g, void *const *a, v
     h.cfg = find_shape(tl.bx, tl.by, tl.waves)->id;
     h.t = tl.t;
     h.maxpasses = z.maxpasses;
+    h.order = team > 0 ? 1 : 0;
+    h.team = team;
     h.grids_off = (int64_t)align16(sizeof(jac::BatchHeader));
     h.items_off = h.grids_off + (int64_t)align16((size_t)n * sizeof(jac::BatchGrid));
     h.pass_off = h.items_off + (int64_t)align16((size_t)z.nitems * sizeof(jac::BatchItem));
@@ -910,18 +924,68 @@ int jacobi_batched_plan(int dtype, int n, const jac_grid_t *g, void *const *a, v
         h.max_shell = std::max<int64_t>(h.max_shell, sh);
     }
     int it = 0;
-    for (int pass = 0; pass < z.maxpasses; ++pass) {
-        pass_start[pass] = it;
-        for (int m = 0; m < n; ++m) {
-            if (pass >= plans[m].passes)
-                continue;
-            for (int tile_i = 0; tile_i < plans[m].tiles; ++tile_i)
-                items[it++] = jac::BatchItem{m, pass, tile_i, 0};
+    if (team == 0) {
+        for (int pass = 0; pass < z.maxpasses; ++pass) {
+            pass_start[pass] = it;
+            for (int m = 0; m < n; ++m) {
+                if (pass >= plans[m].passes)
+                    continue;
+                for (int tile_i = 0; tile_i < plans[m].tiles; ++tile_i)
+                    items[it++] = jac::BatchItem{m, pass, tile_i, 0};
+            }
         }
+    } else {
+        const GridPlan &gp = plans[0];
+        const int P = gp.passes, nq = gp.tp.nkc, nij = gp.tp.nti * gp.tp.ntj;
+        for (int seg = 0; seg < P; seg += team) {
+            const int pe = std::min(P, seg + team);
+            for (int w = 0; w < nq + (pe - seg) - 1; ++w)
+                for (int pass = seg; pass < pe; ++pass) {
+                    const int q = w - (pass - seg);
+                    if (q < 0 || q >= nq)
+                        continue;
+                    for (int ij = 0; ij < nij; ++ij)
+                        items[it++] = jac::BatchItem{0, pass, q * nij + ij, 0};
+                }
+        }
+        // pass ranges do not exist in this order (lockstep runs are refused)
+        for (int pass = 0; pass < z.maxpasses; ++pass)
+            pass_start[pass] = 0;
     }
     pass_start[z.maxpasses] = it;
     memcpy(img, &h, sizeof h);
     return done(JAC_OK);
+}
+
+int jacobi_batched_plan(int dtype, int n, const jac_grid_t *g, void *const *a, void *const *b,
+                        const int *T, const jac_tile_t *tile, void *plan_host, size_t plan_bytes,
+                        int *out_idx_host)
+{
+    g_err.clear();
+    return build_plan(dtype, n, g, a, b, T, tile, plan_host, plan_bytes, out_idx_host, 0);
+}
+
+size_t jacobi_pipelined_plan_bytes(int dtype, const jac_grid_t *g, int T, const jac_tile_t *tile)
+{
+    g_err.clear();
+    jac_tile_t req = tile ? *tile : jac_tile_t{0, 0, 0, 0, 0};
+    if (req.kchunk == 0)
+        req.kchunk = PIPELINE_KCHUNK;
+    return jacobi_batched_plan_bytes(dtype, 1, g, &T, &req);
+}
+
+int jacobi_pipelined_plan(int dtype, const jac_grid_t *g, void *a, void *b, int T, int team,
+                          const jac_tile_t *tile, void *plan_host, size_t plan_bytes,
+                          int *out_idx_host)
+{
+    g_err.clear();
+    if (team < 1 || team > 1024)
+        return fail(JAC_EARG, "team = %d outside 1..1024", team);
+    jac_tile_t req = tile ? *tile : jac_tile_t{0, 0, 0, 0, 0};
+    if (req.kchunk == 0)
+        req.kchunk = PIPELINE_KCHUNK;
+    void *aa[1] = {a}, *bb[1] = {b};
+    return build_plan(dtype, 1, g, aa, bb, &T, &req, plan_host, plan_bytes, out_idx_host, team);
 }
 
 static int read_header(const void *plan_host, jac::BatchHeader *h)
@@ -955,6 +1019,8 @@ int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws, si
         return fail(JAC_EARG, "plan_dev must be a 16-byte aligned device copy of the plan");
     if (mode != JAC_BATCH_RELAXED && mode != JAC_BATCH_LOCKSTEP)
         return fail(JAC_EARG, "mode must be JAC_BATCH_RELAXED or JAC_BATCH_LOCKSTEP");
+    if (h.order != 0 && mode != JAC_BATCH_RELAXED)
+        return fail(JAC_EARG, "a pipelined plan runs in relaxed mode only");
     const size_t need = (size_t)(h.ntiles + 2) * sizeof(int);
     if (!ws || ws_bytes < need)
         return fail(JAC_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);

@@ -74,9 +74,11 @@ KernInfo tb_info_trace_f32(int cfg, int depth);
 // [BatchHeader][BatchGrid x n][BatchItem x nitems][int pass_start x (maxpasses+1)]
 constexpr uint32_t BATCH_MAGIC = 0x4a414342u;  // "JACB"
 
+// order: 0 = items pass by pass (any run mode); 1 = pipelined wavefronts over
+// (pass, k chunk), relaxed mode only.
 struct BatchHeader {
     uint32_t magic;
-    int dtype, n, nitems, ntiles, cfg, t, maxpasses;
+    int dtype, n, nitems, ntiles, cfg, t, maxpasses, order, team;
     int64_t grids_off, items_off, pass_off, total_bytes, max_shell;
 };
 
@@ -89,7 +91,9 @@ struct BatchGrid {
     int T, passes, tiles, counter_off;
 };
 
-// One block of one pass of one grid.  Items are ordered pass by pass.
+// One block of one pass of one grid.  Items are ordered pass by pass, or in
+// pipeline wavefronts; in either order every block an item waits on comes
+// earlier.
 struct BatchItem {
     int grid, pass, tile, pad;
 };

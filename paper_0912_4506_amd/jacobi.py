@@ -253,6 +253,39 @@ class BatchPlan:
         return bool(self.ws[-4:].view(torch.int32).item())
 
 
+class PipelinePlan(BatchPlan):
+    """Pipelined temporal blocking of one grid (jacobi_pipelined_plan): T
+    sweeps as passes of t sweeps per block, segments of `team` passes
+    streaming through k chunks of `kchunk` planes one chunk apart.  Runs in
+    relaxed mode only; results()[0] holds level T."""
+
+    def __init__(self, a, b, T, team=4, t=1, bx=0, by=0, kchunk=0, waves=0):
+        _same(a, b)
+        self.a, self.b = [a], [b]
+        self.dtype = a.dtype
+        lib = _lib.load()
+        code = dtype_code(a)
+        g = grid_of(a)
+        tile = _tile(t, bx, by, kchunk, waves)
+        nbytes = lib.jacobi_pipelined_plan_bytes(code, ctypes.byref(g), int(T), ctypes.byref(tile))
+        if nbytes == 0:
+            check(_lib.JAC_EARG)
+        self._host = (ctypes.c_ubyte * nbytes)()
+        self.out_idx = (ctypes.c_int * 1)()
+        check(lib.jacobi_pipelined_plan(code, ctypes.byref(g), _ptr(a), _ptr(b), int(T), int(team),
+                                        ctypes.byref(tile), self._host, nbytes, self.out_idx))
+        self.plan_dev = torch.frombuffer(bytearray(self._host), dtype=torch.uint8).to(a.device)
+        ws = lib.jacobi_batched_workspace(self._host)
+        self.ws = torch.zeros(max(ws, 8), dtype=torch.uint8, device=a.device)
+        self.device = a.device
+
+
+def pipelined(a, b, T, team=4, t=1, bx=0, by=0, kchunk=0, waves=0):
+    """Level T of grid a by pipelined temporal blocking; returns the tensor
+    (a or b) that holds it."""
+    return PipelinePlan(a, b, T, team, t, bx, by, kchunk, waves).run("relaxed").results()[0]
+
+
 def batched(grids_a, grids_b, Ts, t=None, bx=0, by=0, kchunk=0, mode="relaxed", waves=0):
     """Level T[m] of every grid m (one launch); returns the result tensors."""
     return BatchPlan(grids_a, grids_b, Ts, t, bx, by, kchunk, waves).run(mode).results()

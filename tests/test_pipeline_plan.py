@@ -1,0 +1,126 @@
+"""The pipelined schedule's plan image, on the CPU (jacobi_pipelined_plan
+only writes host memory): every (pass, block) appears once, and every block
+an item waits on (the 27 neighbours of the previous pass) comes earlier in
+the item order -- the condition that keeps relaxed-mode waits from
+deadlocking.  The pass-by-pass order of a one-grid batch is checked too."""
+import ctypes
+import struct
+
+import pytest
+
+from paper_0912_4506_amd import _lib
+from paper_0912_4506_amd._lib import Grid, Tile, JAC_EARG
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+HDR = struct.Struct("<I9i5q")           # magic, dtype .. team, grids_off .. max_shell
+GRID = struct.Struct("<QQqq12i")        # a, b, sy, sz, nx .. counter_off
+
+
+def parse(buf):
+    raw = bytes(buf)
+    h = HDR.unpack_from(raw, 0)
+    nitems, order, team = h[3], h[8], h[9]
+    grids_off, items_off = h[10], h[11]
+    g = GRID.unpack_from(raw, grids_off)
+    nti, ntj, nkc, passes = g[7], g[8], g[9], g[13]
+    items = [struct.unpack_from("<4i", raw, items_off + 16 * n)[:3] for n in range(nitems)]
+    return dict(order=order, team=team, nti=nti, ntj=ntj, nkc=nkc, passes=passes, items=items)
+
+
+def plan(lib, shape, T, team, t, kchunk, bx=64, by=72, waves=12, dtype=1):
+    nx, ny, nz = shape
+    g = Grid(nx, ny, nz, 0, 0)
+    tile = Tile(t, bx, by, kchunk, waves)
+    n = lib.jacobi_pipelined_plan_bytes(dtype, ctypes.byref(g), T, ctypes.byref(tile))
+    assert n > 0, lib.jacobi_last_error()
+    buf = (ctypes.c_ubyte * n)()
+    out = (ctypes.c_int * 1)()
+    rc = lib.jacobi_pipelined_plan(dtype, ctypes.byref(g), ctypes.c_void_p(1 << 20),
+                                   ctypes.c_void_p(1 << 34), T, team, ctypes.byref(tile), buf, n, out)
+    assert rc == 0, lib.jacobi_last_error()
+    return parse(buf), out[0], buf
+
+
+def check_order(p):
+    pos = {}
+    for n, (grid, pas, tile) in enumerate(p["items"]):
+        assert grid == 0
+        assert (pas, tile) not in pos
+        pos[(pas, tile)] = n
+    nti, ntj, nkc = p["nti"], p["ntj"], p["nkc"]
+    assert len(pos) == p["passes"] * nti * ntj * nkc
+    for (pas, tile), n in pos.items():
+        if pas == 0:
+            continue
+        ti, tj, tk = tile % nti, tile // nti % ntj, tile // (nti * ntj)
+        for dk in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    a, b, c = ti + di, tj + dj, tk + dk
+                    if 0 <= a < nti and 0 <= b < ntj and 0 <= c < nkc:
+                        assert pos[(pas - 1, (c * ntj + b) * nti + a)] < n
+
+
+@pytest.mark.parametrize("shape,T,team,t,kchunk", [
+    ((200, 150, 120), 13, 4, 1, 16),
+    ((200, 150, 120), 13, 1, 2, 8),
+    ((130, 70, 64), 20, 7, 1, 4),
+    ((64, 64, 33), 9, 3, 3, 5),
+    ((64, 64, 33), 9, 100, 1, 16),
+])
+def test_pipelined_order_respects_dependencies(lib, shape, T, team, t, kchunk):
+    p, out_idx, _ = plan(lib, shape, T, team, t, kchunk)
+    assert p["order"] == 1 and p["team"] == team
+    assert p["passes"] == -(-T // t) and out_idx == p["passes"] % 2
+    assert p["nkc"] == -(-shape[2] // kchunk)
+    check_order(p)
+    # within a segment, pass seg+s runs s chunks behind pass seg: the first
+    # item of a later pass of the segment comes after its predecessor's item
+    # on the next chunk
+    firsts = {}
+    for n, (_, pas, tile) in enumerate(p["items"]):
+        firsts.setdefault(pas, n)
+    assert all(firsts[q] < firsts[q + 1] for q in range(p["passes"] - 1))
+
+
+def test_batch_order_respects_dependencies(lib):
+    g = Grid(130, 70, 64, 0, 0)
+    tile = Tile(2, 64, 72, 16, 12)
+    T = (ctypes.c_int * 1)(7)
+    n = lib.jacobi_batched_plan_bytes(1, 1, ctypes.byref(g), T, ctypes.byref(tile))
+    buf = (ctypes.c_ubyte * n)()
+    out = (ctypes.c_int * 1)()
+    A = (ctypes.c_void_p * 1)(1 << 20)
+    B = (ctypes.c_void_p * 1)(1 << 34)
+    assert lib.jacobi_batched_plan(1, 1, ctypes.byref(g), A, B, T, ctypes.byref(tile), buf, n,
+                                   out) == 0
+    p = parse(buf)
+    assert p["order"] == 0
+    check_order(p)
+
+
+def test_pipelined_argument_checks(lib):
+    g = Grid(40, 40, 40, 0, 0)
+    tile = Tile(1, 64, 72, 8, 12)
+    n = lib.jacobi_pipelined_plan_bytes(1, ctypes.byref(g), 10, ctypes.byref(tile))
+    buf = (ctypes.c_ubyte * n)()
+    out = (ctypes.c_int * 1)()
+    for team in (0, -3, 2000):
+        assert lib.jacobi_pipelined_plan(1, ctypes.byref(g), ctypes.c_void_p(1 << 20),
+                                         ctypes.c_void_p(1 << 34), 10, team, ctypes.byref(tile),
+                                         buf, n, out) == JAC_EARG
+    assert lib.jacobi_pipelined_plan(1, ctypes.byref(g), ctypes.c_void_p(1 << 20),
+                                     ctypes.c_void_p(1 << 34), 10, 2, ctypes.byref(tile), buf, n - 16,
+                                     out) != 0
+    # a pipelined plan refuses lockstep runs before any HIP call
+    p, _, buf = plan(lib, (40, 40, 40), 10, 2, 1, 8)
+    ws = lib.jacobi_batched_workspace(buf)
+    assert ws > 0
+    rc = lib.jacobi_batched_run(buf, ctypes.c_void_p(1 << 36), ctypes.c_void_p(1 << 38), ws,
+                                _lib.JAC_BATCH_LOCKSTEP, None)
+    assert rc == JAC_EARG and "relaxed" in lib.jacobi_last_error().decode()
