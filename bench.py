@@ -435,8 +435,8 @@ def main():
     ap.add_argument("--skip-f64", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); there is no multi-GPU "
-              "path in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     ensure_built()
     fn = {"metric": bench_metric, "batched": bench_batched, "adjoint": bench_adjoint,

@@ -87,7 +87,7 @@ enum {
     JAC_EARG = -1,         /* invalid argument (see jacobi_last_error) */
     JAC_EHIP = -2,         /* the HIP runtime returned an error */
     JAC_EWORKSPACE = -3,   /* workspace missing or too small */
-    JAC_EUNSUPPORTED = -4  /* valid request this build has no kernel for */
+    JAC_EUNSUPPORTED = -4  /* valid request the library has no kernel for */
 };
 
 /* Library version (JACOBI_ABI_VERSION of the build). */
