@@ -91,3 +91,42 @@ def test_batch_config_64_grids(jac):
     torch.cuda.synchronize()
     for m, (u, out) in enumerate(zip(us, plan.results())):
         assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, 50)), m
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_batched_random_configs(jac, case):
+    """Seeded random batches (shapes, sweep counts, depth, block shape, k
+    chunk, FP32 or FP64) in relaxed mode, twice in a row on the same plan:
+    the publication of finished blocks between workgroups (write-through
+    stores, counters, acquire) must give the sequential result every time."""
+    rng = np.random.default_rng(1000 + case)
+    n = int(rng.integers(1, 9))
+    shapes = [tuple(int(x) for x in rng.integers(1, 120, size=3)) for _ in range(n)]
+    Ts = [int(x) for x in rng.integers(0, 30, size=n)]
+    menu = jac.tile_menu(torch.float64)
+    bx, by, w = menu[int(rng.integers(0, len(menu)))]
+    t = int(rng.integers(1, 6))
+    kc = int(rng.choice([0, 8, 16, 40]))
+    dtype = torch.float64 if case % 3 else torch.float32
+    us, a, b = make_batch(shapes, seed=case, dtype=dtype)
+    try:
+        plan = jac.BatchPlan(a, b, Ts, t=t, bx=bx, by=by, waves=w, kchunk=kc)
+    except Exception as e:      # a block too small for the depth, or too little LDS
+        from paper_0912_4506_amd._lib import JacobiError, JAC_EUNSUPPORTED
+        assert isinstance(e, JacobiError) and e.code == JAC_EUNSUPPORTED, e
+        pytest.skip(f"refused: {e}")
+    refs = [oracle.sweeps(u.astype(np.float32).astype(np.float64) if dtype == torch.float32 else u, T)
+            for u, T in zip(us, Ts)]
+    for rep in range(2):
+        if rep:
+            for x, u in zip(a, us):
+                x.copy_(torch.from_numpy(u).to("cuda", dtype))
+        plan.run("relaxed")
+        torch.cuda.synchronize()
+        assert not plan.wait_error()
+        for m, (ref, out) in enumerate(zip(refs, plan.results())):
+            got = out.cpu().numpy().astype(np.float64)
+            if dtype == torch.float64:
+                assert np.array_equal(got, ref), (case, rep, m, shapes[m], Ts[m], t, bx, by, w, kc)
+            else:
+                assert np.max(np.abs(got - ref)) <= 1e-5, (case, rep, m)
