@@ -79,6 +79,7 @@ def cpu_baseline(u, T, lups_per_sweep, target_s=12.0):
     """The CPU oracle, as it stands, on the host cores: the whole grid for as
     many of the T sweeps as fit about target_s seconds."""
     import oracle
+    cores = oracle.max_threads()
     t0 = time.perf_counter()
     oracle.sweeps(u, 2)
     t1 = time.perf_counter()
@@ -96,9 +97,10 @@ def cpu_baseline(u, T, lups_per_sweep, target_s=12.0):
     t2 = time.perf_counter()
     oracle.sweeps(u, 1, nthreads=1)
     dt1 = max((t2 - t1) - (time.perf_counter() - t2), 1e-6)
+    oracle.max_threads(cores)     # the oracle's thread count is process-wide: restore it
     n = round(u.shape[0] - 2)
     return {"value": round(lups_per_sweep * sweeps / dt / 1e9, 4), "unit": "GLUP/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"{n}^3 FP64 grid, {sweeps} of the {T} sweeps, one run ({dt:.1f} s)",
             "single_thread": round(lups_per_sweep / dt1 / 1e9, 4)}
 

@@ -559,9 +559,12 @@ int jacobi_plain(int dtype, const jac_grid_t *g, void *a, void *b, int T, void *
     if (T == 0)
         return JAC_OK;
     hipStream_t st = (hipStream_t)stream;
-    // k-chunk: long streams (contiguous reads), but enough blocks to fill the chip
-    const int64_t strips = ((geo.nx + 511) / 512) * ((geo.ny + 7) / 8);
-    int64_t nkc = ((int64_t)device_facts().cus + strips - 1) / strips;
+    // k-chunk: long streams (contiguous reads), but enough blocks to fill the
+    // chip (with 128-thread strips, two per CU)
+    const int nt = jac::plain_threads(geo.nx);
+    const int64_t strips = ((geo.nx + 2 * nt - 1) / (2 * nt)) * ((geo.ny + 7) / 8);
+    const int64_t slots = (int64_t)device_facts().cus * (nt == 128 ? 2 : 1);
+    int64_t nkc = (slots + strips - 1) / strips;
     nkc = std::max<int64_t>(1, std::min<int64_t>(nkc, geo.nz));
     const int kchunk = (int)((geo.nz + nkc - 1) / nkc);
     jac::PlainArgs p{(int)geo.nx, (int)geo.ny, (int)geo.nz, kchunk, geo.sy, geo.sz};

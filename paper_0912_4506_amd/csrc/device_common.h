@@ -26,6 +26,27 @@ __device__ __forceinline__ float div6(float s)
     return s * (1.0f / 6.0f);
 }
 
+// Workgroup ids reach the eight XCDs round robin (id mod 8), and each XCD has
+// its own L2.  Remap so that XCD x works through a contiguous range of
+// logical blocks: blocks that share halo cells then run on the same L2 at the
+// same time.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int q = n >> 3, rem = n & 7, x = b & 7, idx = b >> 3;
+    return x * q + min(x, rem) + idx;
+}
+
+// The 3-D block index of a launch after xcd_remap (x fastest).
+__device__ __forceinline__ void remapped_block(int &bx, int &by, int &bz)
+{
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int total = gx * gy * gridDim.z;
+    const int l = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), total);
+    bx = l % gx;
+    by = (l / gx) % gy;
+    bz = l / (gx * gy);
+}
+
 // ------------------------------------------------------- cross-lane moves --
 // DPP wave shifts (GFX9 wave_shr:1 / wave_shl:1): lane l receives the value
 // of lane l-1 (shr) or l+1 (shl); bound_ctrl makes the lane with no source

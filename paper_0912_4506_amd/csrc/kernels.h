@@ -35,6 +35,10 @@ struct GridArgs {
     int64_t nx, ny, nz, sy, sz;
 };
 
+// Threads per block of the plain sweep for an interior width nx (its strips
+// are 2 * threads cells wide).
+int plain_threads(int64_t nx);
+
 struct PlainArgs {
     int nx, ny, nz, kchunk;
     int64_t sy, sz;

@@ -20,22 +20,33 @@ namespace jac {
 
 // ------------------------------------------------------------ plain sweep --
 // One sweep, one pass over memory (the standard Jacobi of Sect. 1.1).  A block
-// of 256 threads owns a strip of PLAIN_ROWS rows by 512 cells along i (two
-// cells per thread) and streams through a chunk of k planes.  The strip's rows
+// of NT threads (256 or 128) owns a strip of PLAIN_ROWS rows by 2*NT cells
+// along i (two cells per thread) and streams through a chunk of k planes.  The strip's rows
 // of plane k-1, k and k+1 stay in registers, so each step reads one new plane
 // of the strip (PLAIN_ROWS + 2 whole row segments, contiguous in memory) and
 // writes one; i-neighbours at the thread's ends are read through the cache.
 // Coordinates of loads are clamped into the array; stores are predicated.
 constexpr int PLAIN_ROWS = 8;
 
-template <typename real>
-__global__ __launch_bounds__(256) void plain_kernel(const real *__restrict__ A,
-                                                    real *__restrict__ B, PlainArgs p)
+// Strip width: 512 cells (256 threads) unless 256-cell strips leave fewer
+// idle lanes along i (e.g. nx = 256 or 768).
+int plain_threads(int64_t nx)
+{
+    const int64_t idle512 = (nx + 511) / 512 * 512 - nx, idle256 = (nx + 255) / 256 * 256 - nx;
+    return idle256 < idle512 ? 128 : 256;
+}
+
+template <typename real, int NT>
+__global__ __launch_bounds__(NT) void plain_kernel(const real *__restrict__ A,
+                                                   real *__restrict__ B, PlainArgs p)
 {
     constexpr int RB = PLAIN_ROWS;
-    const int i0 = 1 + blockIdx.x * 512 + 2 * threadIdx.x;
-    const int j0 = 1 + blockIdx.y * RB;
-    const int k0 = 1 + blockIdx.z * p.kchunk;
+    // strips adjacent in j share their halo rows: keep them on one XCD's L2
+    int bx, by, bz;
+    remapped_block(bx, by, bz);
+    const int i0 = 1 + bx * (2 * NT) + 2 * threadIdx.x;
+    const int j0 = 1 + by * RB;
+    const int k0 = 1 + bz * p.kchunk;
     const int k1 = min(k0 + p.kchunk, p.nz + 1);
     const int ia = min(i0, p.nx + 1), ib = min(i0 + 1, p.nx + 1);
     const int iw = min(i0 - 1, p.nx + 1), ie = min(i0 + 2, p.nx + 1);
@@ -159,10 +170,13 @@ __global__ __launch_bounds__(256) void residual_kernel(const double *__restrict_
                                                        double *__restrict__ partial, PlainArgs p)
 {
     __shared__ double red[256];
-    // one cell per thread: 256 consecutive cells of RB rows, streamed in k
-    const int i = 1 + blockIdx.x * 256 + threadIdx.x;
-    const int j0 = 1 + blockIdx.y * RB;
-    const int k0 = 1 + blockIdx.z * p.kchunk;
+    // one cell per thread: 256 consecutive cells of RB rows, streamed in k;
+    // strips adjacent in j (sharing halo rows) stay on one XCD
+    int bx, by, bz;
+    remapped_block(bx, by, bz);
+    const int i = 1 + bx * 256 + threadIdx.x;
+    const int j0 = 1 + by * RB;
+    const int k0 = 1 + bz * p.kchunk;
     const int k1 = min(k0 + p.kchunk, p.nz + 1);
     const int ic = min(i, p.nx + 1), iw = min(i - 1, p.nx + 1), ie = min(i + 1, p.nx + 1);
     // interior masks of the three i positions (FUSED only)
@@ -249,7 +263,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const double *__restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        partial[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+        partial[((int64_t)bz * gridDim.y + by) * gridDim.x + bx] = red[0];
 }
 
 // Fill and update kernels: blocks own RES_ROWS rows x 256 cells and a k chunk
@@ -438,9 +452,13 @@ __global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src
 template <typename real>
 hipError_t launch_plain(const real *a, real *b, const PlainArgs &p, hipStream_t st)
 {
-    dim3 grid((p.nx + 511) / 512, (p.ny + PLAIN_ROWS - 1) / PLAIN_ROWS,
+    const int nt = plain_threads(p.nx);
+    dim3 grid((p.nx + 2 * nt - 1) / (2 * nt), (p.ny + PLAIN_ROWS - 1) / PLAIN_ROWS,
               (p.nz + p.kchunk - 1) / p.kchunk);
-    hipLaunchKernelGGL(plain_kernel<real>, grid, dim3(256), 0, st, a, b, p);
+    if (nt == 256)
+        hipLaunchKernelGGL((plain_kernel<real, 256>), grid, dim3(256), 0, st, a, b, p);
+    else
+        hipLaunchKernelGGL((plain_kernel<real, 128>), grid, dim3(128), 0, st, a, b, p);
     return hipGetLastError();
 }
 

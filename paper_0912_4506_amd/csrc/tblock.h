@@ -39,16 +39,6 @@ __device__ __forceinline__ AxisTile axis_tile(int blk, int n, int w, int h)
     return t;
 }
 
-// Workgroup ids reach the eight XCDs round robin (id mod 8), and each XCD has
-// its own L2.  Remap so that XCD x works through a contiguous range of
-// logical blocks: blocks that share halo cells then run on the same L2 at the
-// same time.
-__device__ __forceinline__ int xcd_remap(int b, int n)
-{
-    const int q = n >> 3, rem = n & 7, x = b & 7, idx = b >> 3;
-    return x * q + min(x, rem) + idx;
-}
-
 // The exchange buffer is double-buffered (one barrier per stream step) when
 // two copies fit in the 160 KiB of LDS a gfx950 workgroup may use, less 1 KiB
 // kept for the kernels' static LDS.
