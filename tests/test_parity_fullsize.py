@@ -7,6 +7,8 @@ benchmark times.
   one from their domain of dependence.  The samples include the shell
   corners, the edges of the blocks and k chunks the default plan uses, and
   random interior cells.
+* The same 512^3 grid by the pipelined schedule (bitwise) and in FP32 at the
+  default blocking (within 1e-5 of the oracle on the FP32-rounded input).
 * 768^3, the refinement's inner solve: 50 FP32 sweeps with a right-hand side
   at the library's default depth against the oracle's full FP64 run, and the
   FP64 residual and the fused update-and-residual bitwise over the whole grid.
@@ -84,6 +86,37 @@ def test_512_blocked_default_sampled(jac, grid512, t):
     got = sampled(out, pts)
     bad = [(p, g, r) for p, g, r in zip(pts, got, ref) if not g == r]
     assert not bad, bad[:5]
+
+
+def test_512_pipelined_sampled(jac, grid512):
+    """The pipelined schedule at the workload size (two passes in flight,
+    4 sweeps per item, 32-plane chunks), bitwise at the sampled cells."""
+    u, pts, ref = grid512
+    a = dev(u)
+    b = torch.full_like(a, float("nan"))
+    out = jac.pipelined(a, b, T, team=2, t=4, kchunk=32)
+    torch.cuda.synchronize()
+    assert np.array_equal(sampled(out, pts), ref)
+
+
+@pytest.fixture(scope="module")
+def grid512_f32():
+    u = inputs.grid(N, N, N, seed=0).astype(np.float32).astype(np.float64)
+    pts = samples()[::3]
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        ref = list(ex.map(lambda p: oracle.point(u, T, *p), pts))
+    return u, pts, np.array(ref)
+
+
+def test_512_fp32_blocked_default_sampled(jac, grid512_f32):
+    """FP32 at the workload size with the library's default blocking: within
+    1e-5 of the FP64 oracle run on the FP32-rounded input."""
+    u, pts, ref = grid512_f32
+    a = dev(u, torch.float32)
+    b = torch.empty_like(a)
+    out = jac.tblock(a, b, T)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(sampled(out, pts).astype(np.float64) - ref)) <= 1e-5
 
 
 def test_768_rhs_fp32_default(jac):
