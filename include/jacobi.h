@@ -192,6 +192,42 @@ int jacobi_pipelined_plan(int dtype, const jac_grid_t *g, void *a, void *b, int 
                           int team, const jac_tile_t *tile, void *plan_host,
                           size_t plan_bytes, int *out_idx_host);
 
+/* Compressed single grid: T sweeps in ONE array instead of two, the
+ * "compressed grid" of Sect. 1.2 (results written to a location shifted
+ * against the one they were read from, alternate passes shifting back), with
+ * t sweeps fused per pass as in jacobi_tblock.
+ *  Layout: with S = tile->t (1..JAC_MAX_DEPTH, required: the layout depends
+ *    on it) the array holds (nx+2+S) x (ny+2+S) x (nz+2) cells.  g gives the
+ *    interior nx, ny, nz and the array's strides (0 = dense: sy = nx+2+S,
+ *    sz = sy*(ny+2+S); else sy >= nx+2+S, sz >= sy*(ny+2+S)); u points at
+ *    its element (0, 0, 0).  Frame 0 holds grid cell (i, j, k) at
+ *    u[(i+S) + (j+S)*sy + k*sz], frame 1 at u[i + j*sy + k*sz].
+ *  On entry frame 0 holds level 0 (shell included).  Pass p (ceil(T/t)
+ *    passes, depths as for jacobi_tblock) reads frame p mod 2 and writes the
+ *    other: the shift of (-S,-S,0) or (+S,+S,0) cells means that a block
+ *    overwrites only inputs of its own and of its three neighbours on one
+ *    side, so each workgroup waits, plane by plane, until those have read the
+ *    plane it writes (per-block progress counters, bounded waits).  On
+ *    return *out_frame = (number of passes) mod 2 names the frame holding
+ *    level T, shell included, bitwise as jacobi_tblock computes it; the other
+ *    elements of the array are undefined.  T = 0 enqueues nothing, frame 0.
+ *  tile: t as above; bx, by, waves as for jacobi_tblock (64-wide blocks
+ *    whose valid widths bx-2d and by-2d are at least d+t at every pass
+ *    depth d, else JAC_EUNSUPPORTED; 0 = library choice); kchunk >= t or 0.
+ *  ws: device workspace of jacobi_compressed_workspace(dtype, g, T, tile)
+ *    bytes (0 on invalid arguments, see jacobi_last_error), 256-byte
+ *    aligned, not overlapping the array: per-pass counters, copies of the
+ *    2S+1 planes around each inner k chunk boundary, and the saved shell
+ *    (about (2S+1)/kchunk of the array plus O(N^2)).  Its first int is an
+ *    error flag: a wait that has not ended after about 2^20 polls gives up
+ *    and sets it to 1 (results are then invalid); the caller may read it
+ *    after synchronising. */
+size_t jacobi_compressed_workspace(int dtype, const jac_grid_t *g, int T,
+                                   const jac_tile_t *tile);
+int jacobi_compressed(int dtype, const jac_grid_t *g, void *u, int T,
+                      const jac_tile_t *tile, void *ws, size_t ws_bytes,
+                      void *stream, int *out_frame);
+
 /* Mixed-precision refinement helpers (outer FP64 loop around an FP32 Jacobi
  * inner solve; the refinement is not in the paper, the operator is the
  * Laplace system whose fixed point the Jacobi iteration of Sect. 1.1 seeks).

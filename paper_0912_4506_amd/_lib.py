@@ -64,6 +64,9 @@ SIGNATURES = {
     "jacobi_pipelined_plan_bytes": ([ctypes.c_int, _GP, ctypes.c_int, _TP], ctypes.c_size_t),
     "jacobi_pipelined_plan": ([ctypes.c_int, _GP, _P, _P, ctypes.c_int, ctypes.c_int, _TP, _P,
                                ctypes.c_size_t, _IP], ctypes.c_int),
+    "jacobi_compressed_workspace": ([ctypes.c_int, _GP, ctypes.c_int, _TP], ctypes.c_size_t),
+    "jacobi_compressed": ([ctypes.c_int, _GP, _P, ctypes.c_int, _TP, _P, ctypes.c_size_t, _P, _IP],
+                          ctypes.c_int),
     "jacobi_tile_menu": ([ctypes.c_int, _IP, ctypes.c_int], ctypes.c_int),
     "jacobi_autotune": ([ctypes.c_int, _GP, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _TP,
                          ctypes.POINTER(ctypes.c_float), _P], ctypes.c_int),

@@ -533,6 +533,169 @@ int check_pair(int dtype, const Geo &g, const void *a, const void *b)
     return JAC_OK;
 }
 
+// ------------------------------------------------------- compressed grid --
+// A compressed run keeps the grid in one array of (nx+2+S) x (ny+2+S) x
+// (nz+2) cells, S = t, in two frames: frame 0 holds cell (i, j, k) at
+// (i+S, j+S, k), frame 1 at (i, j, k).  Even passes read frame 0 and write
+// frame 1, odd passes the reverse.  Each pass also needs copies of the planes
+// around its inner k chunk boundaries (taken before the pass) and rewrites
+// the shell in the frame it wrote from a saved copy.
+struct CompPlan {
+    const jac::TileShape *shape = nullptr;
+    int S = 0, P = 0, kchunk = 0, nkc = 0, maxitems = 0;
+    int64_t span = 0;                        // elements of the array
+    size_t nints = 0, snap_off = 0, store_off = 0, bytes = 0;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Geometry of the frames: strides of the padded array (0 = dense).
+int check_comp_grid(const jac_grid_t *g, int S, Geo *out)
+{
+    if (!g)
+        return fail(JAC_EARG, "grid descriptor is NULL");
+    jac_grid_t d = *g;
+    if (d.sy == 0)
+        d.sy = d.nx + 2 + S;
+    if (d.sz == 0)
+        d.sz = d.sy * (d.ny + 2 + S);
+    int rc;
+    if ((rc = check_grid(&d, out)))
+        return rc;
+    if (out->sy < out->nx + 2 + S)
+        return fail(JAC_EARG, "sy = %lld is below nx+2+t = %lld", (long long)out->sy,
+                    (long long)(out->nx + 2 + S));
+    if (out->sz < out->sy * (out->ny + 2 + S))
+        return fail(JAC_EARG, "sz = %lld is below sy*(ny+2+t) = %lld", (long long)out->sz,
+                    (long long)(out->sy * (out->ny + 2 + S)));
+    return JAC_OK;
+}
+
+int plan_compressed(int dtype, const jac_grid_t *g, int T, const jac_tile_t *tile, Geo *geo,
+                    CompPlan *cp)
+{
+    if (!tile || tile->t < 1 || tile->t > JAC_MAX_DEPTH)
+        return fail(JAC_EARG, "a compressed run needs tile->t in 1..%d (the frame shift is t)",
+                    JAC_MAX_DEPTH);
+    const int S = tile->t;
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_comp_grid(g, S, geo)))
+        return rc;
+    if (T < 0)
+        return fail(JAC_EARG, "T = %d is negative", T);
+    jac_tile_t want = *tile, tl;
+    if ((rc = resolve_tile(dtype, &want, 0, &tl, nullptr, KIND_PLAIN)))
+        return rc;
+    const jac::TileShape *shape = find_shape(tl.bx, tl.by, tl.waves);
+    if (shape->ci != 1)
+        return fail(JAC_EUNSUPPORTED, "a compressed run needs a 64-wide block, not %d x %d", tl.bx,
+                    tl.by);
+    if (tl.kchunk > 0 && tl.kchunk < S)
+        return fail(JAC_EARG, "kchunk = %d is below t = %d", tl.kchunk, S);
+    CompPlan c;
+    c.shape = shape;
+    c.S = S;
+    c.P = T > 0 ? (T + S - 1) / S : 0;
+    c.span = (geo->nz + 1) * geo->sz + (geo->ny + 1 + S) * geo->sy + geo->nx + 2 + S;
+    // blocks per pass (the depths of the passes differ by at most one).  A
+    // block's output may overwrite inputs of its nearest neighbours only,
+    // which holds when every valid width is at least depth + S.
+    int64_t nij = 0;
+    for (int pass = 0; pass < std::min(c.P, 2); ++pass) {
+        const int depth = T / c.P + (pass < T % c.P ? 1 : 0);
+        TbPlan tp;
+        if (!plan_ij(*geo, *shape, depth, &tp))
+            return fail(JAC_EUNSUPPORTED, "block %d x %d has no valid cells at depth %d", tl.bx,
+                        tl.by, depth);
+        if (shape->bx() - 2 * tp.hi < depth + S || shape->by() - 2 * depth < depth + S)
+            return fail(JAC_EUNSUPPORTED, "block %d x %d is too small for a compressed run at t = %d",
+                        tl.bx, tl.by, S);
+        nij = std::max<int64_t>(nij, (int64_t)tp.nti * tp.ntj);
+    }
+    // one k chunking for every pass, planned for depth t
+    TbPlan tp;
+    if (!plan_ij(*geo, *shape, S, &tp))
+        return fail(JAC_EUNSUPPORTED, "block %d x %d has no valid cells at depth %d", tl.bx, tl.by,
+                    S);
+    int occ = jac::tblock_occupancy(dtype, shape->id, S, jac::MODE_COMP);
+    plan_k(*geo, device_facts().cus * std::max(occ, 1), &tp, tl.kchunk);
+    c.kchunk = std::max(tp.kchunk, S);
+    c.nkc = (int)((geo->nz + c.kchunk - 1) / c.kchunk);
+    if (nij * c.nkc > INT_MAX / 2)
+        return fail(JAC_EUNSUPPORTED, "too many blocks");
+    c.maxitems = (int)(nij * c.nkc);
+    const size_t esz = elem_size(dtype);
+    c.nints = 1 + (size_t)c.P * (1 + (size_t)c.maxitems);
+    c.snap_off = align256(c.nints * sizeof(int));
+    c.store_off = align256(c.snap_off + (size_t)(c.nkc - 1) * (2 * S + 1) * geo->sz * esz);
+    c.bytes = c.store_off + (size_t)jac::shell_count(grid_args(*geo)) * esz;
+    *cp = c;
+    return JAC_OK;
+}
+
+template <typename real>
+int run_compressed(const Geo &g, real *u, int T, const CompPlan &c, unsigned char *ws,
+                   hipStream_t st)
+{
+    const int S = c.S;
+    int *ints = (int *)ws;
+    real *snap = (real *)(ws + c.snap_off);
+    real *store = (real *)(ws + c.store_off);
+    const int64_t off0 = S + S * g.sy;  // frame 0; frame 1 starts at u
+    const jac::GridArgs ga = grid_args(g);
+    hipError_t e;
+    if ((e = jac::launch_zero_ints(ints, (int64_t)c.nints, st)) ||
+        (e = jac::launch_shell_store<real>(1, u + off0, store, ga, st)))
+        return hip_fail(e, "compressed set-up");
+    for (int pass = 0; pass < c.P; ++pass) {
+        const int depth = T / c.P + (pass < T % c.P ? 1 : 0);
+        TbPlan tp;
+        plan_ij(g, *c.shape, depth, &tp);
+        const int64_t soff = pass % 2 == 0 ? off0 : 0, doff = pass % 2 == 0 ? 0 : off0;
+        // planes [Kb - S, Kb + S] around each inner chunk boundary Kb
+        for (int b = 1; b < c.nkc; ++b) {
+            const int64_t kb = 1 + (int64_t)b * c.kchunk, lo = kb - S;
+            const int64_t hi = std::min<int64_t>(kb + S, g.nz + 1);
+            const int64_t n = std::min<int64_t>((hi - lo + 1) * g.sz, c.span - lo * g.sz);
+            e = hipMemcpyAsync(snap + (int64_t)(b - 1) * (2 * S + 1) * g.sz, u + lo * g.sz,
+                               (size_t)n * sizeof(real), hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess)
+                return hip_fail(e, "boundary plane copy");
+        }
+        jac::TbArgs<real> args{};
+        args.src = u + soff;
+        args.dst = u + doff;
+        args.sy = g.sy;
+        args.sz = g.sz;
+        args.nx = (int)g.nx;
+        args.ny = (int)g.ny;
+        args.nz = (int)g.nz;
+        args.nti = tp.nti;
+        args.ntj = tp.ntj;
+        args.hi = tp.hi;
+        args.kchunk = c.kchunk;
+        args.snap = snap + soff;
+        args.ticket = ints + 1 + (int64_t)pass * (1 + c.maxitems);
+        args.prog = args.ticket + 1;
+        args.error = ints;
+        args.shift = S;
+        args.dir = pass % 2 == 0 ? 1 : -1;
+        args.spin_limit = 1 << 20;
+        const int nblocks = tp.nti * tp.ntj * c.nkc;
+        if (debug_plans())
+            fprintf(stderr,
+                    "[jacobi] compressed pass %d/%d depth %d block %dx%d w%d: columns %dx%d, "
+                    "k chunk %d planes, %d workgroups\n",
+                    pass + 1, c.P, depth, c.shape->bx(), c.shape->by(), c.shape->waves, tp.nti,
+                    tp.ntj, c.kchunk, nblocks);
+        if ((e = jac::launch_tblock<real>(c.shape->id, depth, jac::MODE_COMP, args, nblocks, st)))
+            return hip_fail(e, "compressed pass launch");
+        if ((e = jac::launch_shell_store<real>(0, u + doff, store, ga, st)))
+            return hip_fail(e, "compressed shell");
+    }
+    return JAC_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI ==
@@ -683,6 +846,48 @@ int jacobi_adjoint(int dtype, const jac_grid_t *g, void *lam_a, void *lam_b, int
     if (rc)
         return rc;
     *out_idx = P % 2;
+    return JAC_OK;
+}
+
+size_t jacobi_compressed_workspace(int dtype, const jac_grid_t *g, int T, const jac_tile_t *tile)
+{
+    g_err.clear();
+    Geo geo;
+    CompPlan c;
+    if (plan_compressed(dtype, g, T, tile, &geo, &c))
+        return 0;
+    return c.bytes;
+}
+
+int jacobi_compressed(int dtype, const jac_grid_t *g, void *u, int T, const jac_tile_t *tile,
+                      void *ws, size_t ws_bytes, void *stream, int *out_frame)
+{
+    g_err.clear();
+    Geo geo;
+    CompPlan c;
+    int rc;
+    if ((rc = plan_compressed(dtype, g, T, tile, &geo, &c)) || (rc = check_ptr(u, dtype, "u")))
+        return rc;
+    if (!out_frame)
+        return fail(JAC_EARG, "out_frame is NULL");
+    if (!ws)
+        return fail(JAC_EWORKSPACE, "workspace is NULL (%zu bytes needed)", c.bytes);
+    if (ws_bytes < c.bytes)
+        return fail(JAC_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, c.bytes);
+    if ((uintptr_t)ws % 256)
+        return fail(JAC_EARG, "workspace is not 256-byte aligned");
+    if (overlap(ws, c.bytes, u, (size_t)c.span * elem_size(dtype)))
+        return fail(JAC_EARG, "workspace overlaps the grid");
+    *out_frame = 0;
+    if (T == 0)
+        return JAC_OK;
+    if (dtype == JAC_F64)
+        rc = run_compressed<double>(geo, (double *)u, T, c, (unsigned char *)ws, (hipStream_t)stream);
+    else
+        rc = run_compressed<float>(geo, (float *)u, T, c, (unsigned char *)ws, (hipStream_t)stream);
+    if (rc)
+        return rc;
+    *out_frame = c.P % 2;
     return JAC_OK;
 }
 

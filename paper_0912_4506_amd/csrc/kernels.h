@@ -27,8 +27,9 @@
 
 namespace jac {
 
-// MODE_BATCH is MODE_PLAIN with agent-scope output stores (see batched_kernel)
-enum { MODE_PLAIN = 0, MODE_RHS = 1, MODE_TRACE = 2, MODE_BATCH = 3 };
+// MODE_BATCH is MODE_PLAIN with agent-scope output stores (see batched_kernel);
+// MODE_COMP reads and writes one array in two frames (see compressed_kernel)
+enum { MODE_PLAIN = 0, MODE_RHS = 1, MODE_TRACE = 2, MODE_BATCH = 3, MODE_COMP = 4 };
 enum { FACES_SAVE = 0, FACES_ZERO = 1, FACES_CLEAR_SUM = 2, FACES_ACCUM = 3, FACES_FINALIZE = 4 };
 
 struct GridArgs {
@@ -56,6 +57,16 @@ struct TbArgs {
     int hi;             // i-halo (>= depth; even when CI is even, for alignment)
     int64_t fstride;    // MODE_TRACE: values per level of the face trace
     int kchunk;         // output planes per workgroup along k
+    // MODE_COMP only: copies of the planes around the k chunk boundaries
+    // (2*shift+1 planes per inner boundary, addressed like src), one progress
+    // counter per block, the ticket counter, the error flag, the frame shift,
+    // the direction of the block order (+1: blocks wait on lower neighbours,
+    // -1: on upper ones) and the polls before a wait gives up
+    const real *snap;
+    int *prog;
+    int *ticket;
+    int *error;
+    int shift, dir, spin_limit;
 };
 
 // A compiled kernel instance: entry point, dynamic LDS bytes, threads per block.
@@ -72,6 +83,8 @@ KernInfo tb_info_rhs_f64(int cfg, int depth);
 KernInfo tb_info_rhs_f32(int cfg, int depth);
 KernInfo tb_info_trace_f64(int cfg, int depth);
 KernInfo tb_info_trace_f32(int cfg, int depth);
+KernInfo tb_info_comp_f64(int cfg, int depth);
+KernInfo tb_info_comp_f32(int cfg, int depth);
 
 // ------------------------------------------------------------- batched runs --
 // Plan image of a batched run (built on the host, uploaded by the caller):
@@ -135,6 +148,11 @@ hipError_t launch_copy_shell(const real *a, real *b, const GridArgs &g, hipStrea
 template <typename real>
 hipError_t launch_batch_shells(const BatchGrid *grids, int n, int64_t max_shell, hipStream_t st);
 hipError_t launch_zero_ints(int *x, int64_t n, hipStream_t st);
+// The whole shell of a grid, edges and corners included, to (save = 1) or
+// from (save = 0) a compact array of shell_count(g) values.
+int64_t shell_count(const GridArgs &g);
+template <typename real>
+hipError_t launch_shell_store(int save, real *grid, real *store, const GridArgs &g, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 // Shell-face helpers of the adjoint (FACES_*): save grid faces into G, zero
 // the grid's faces, clear S, accumulate S += trace levels in order, or write

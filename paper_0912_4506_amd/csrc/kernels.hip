@@ -400,6 +400,50 @@ __global__ void face_finalize_kernel(real *__restrict__ grid, const real *__rest
         grid[face_offset(f, g)] = G[f] + div6(S[f]);
 }
 
+// The whole shell of a grid (six faces with their edges and corners) as one
+// compact array of shell_count(g) values: [k = 0 plane: (j, i)], [k = nz+1],
+// [j = 0: (k, i)], [j = ny+1], [i = 0: (k, j)], [i = nx+1], each face over
+// the full extents (edges and corners appear in several faces).
+__device__ __forceinline__ int64_t shell_offset(int64_t f, const GridArgs &g)
+{
+    const int64_t nxp = g.nx + 2, nyp = g.ny + 2, nzp = g.nz + 2;
+    const int64_t nk = nxp * nyp, nj = nxp * nzp, ni = nyp * nzp;
+    if (f < 2 * nk) {
+        const int64_t u = f % nk;
+        return u % nxp + (u / nxp) * g.sy + (f < nk ? 0 : (g.nz + 1) * g.sz);
+    }
+    f -= 2 * nk;
+    if (f < 2 * nj) {
+        const int64_t u = f % nj;
+        return u % nxp + (u / nxp) * g.sz + (f < nj ? 0 : (g.ny + 1) * g.sy);
+    }
+    f -= 2 * nj;
+    const int64_t u = f % ni;
+    return (u % nyp) * g.sy + (u / nyp) * g.sz + (f < ni ? 0 : g.nx + 1);
+}
+
+int64_t shell_count(const GridArgs &g)
+{
+    const int64_t nxp = g.nx + 2, nyp = g.ny + 2, nzp = g.nz + 2;
+    return 2 * (nxp * nyp + nxp * nzp + nyp * nzp);
+}
+
+// save: store[f] = grid[shell f]; else grid[shell f] = store[f]
+template <typename real>
+__global__ __launch_bounds__(256) void shell_store_kernel(real *__restrict__ grid,
+                                                          real *__restrict__ store, GridArgs g,
+                                                          int64_t n, int save)
+{
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < n;
+         f += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = shell_offset(f, g);
+        if (save)
+            store[f] = grid[o];
+        else
+            grid[o] = store[f];
+    }
+}
+
 // Shell copy a -> b of every grid of a batch: blockIdx.y is the grid.
 template <typename real>
 __global__ void batch_shell_kernel(const BatchGrid *__restrict__ grids)
@@ -470,6 +514,7 @@ static KernInfo tb_info(int cfg, int depth, int mode)
     case MODE_PLAIN: return f64 ? tb_info_plain_f64(cfg, depth) : tb_info_plain_f32(cfg, depth);
     case MODE_RHS: return f64 ? tb_info_rhs_f64(cfg, depth) : tb_info_rhs_f32(cfg, depth);
     case MODE_TRACE: return f64 ? tb_info_trace_f64(cfg, depth) : tb_info_trace_f32(cfg, depth);
+    case MODE_COMP: return f64 ? tb_info_comp_f64(cfg, depth) : tb_info_comp_f32(cfg, depth);
     default: return KernInfo{nullptr, 0, 0};
     }
 }
@@ -715,6 +760,18 @@ hipError_t launch_batch_shells(const BatchGrid *grids, int n, int64_t max_shell,
 }
 template hipError_t launch_batch_shells<float>(const BatchGrid *, int, int64_t, hipStream_t);
 template hipError_t launch_batch_shells<double>(const BatchGrid *, int, int64_t, hipStream_t);
+
+template <typename real>
+hipError_t launch_shell_store(int save, real *grid, real *store, const GridArgs &g, hipStream_t st)
+{
+    const int64_t n = shell_count(g);
+    hipLaunchKernelGGL(shell_store_kernel<real>, dim3(grid_blocks(n)), dim3(256), 0, st, grid,
+                       store, g, n, save);
+    return hipGetLastError();
+}
+template hipError_t launch_shell_store<float>(int, float *, float *, const GridArgs &, hipStream_t);
+template hipError_t launch_shell_store<double>(int, double *, double *, const GridArgs &,
+                                               hipStream_t);
 
 hipError_t launch_zero_ints(int *x, int64_t n, hipStream_t st)
 {

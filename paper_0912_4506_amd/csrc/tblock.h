@@ -123,8 +123,36 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
         fix_j = fix_j || sh_j[r];
     }
 
+    // MODE_COMP: lanes 0..2 name the blocks of the same k chunk whose inputs
+    // this block's output overwrites (the neighbours at -1 along i, j and
+    // both for dir = +1, at +1 for dir = -1), and follow their progress.
+    int dep = -1, got = 0, pend = 0, self = 0;
+    if constexpr (MODE == MODE_COMP) {
+        const int tk = (k0 - 1) / p.kchunk;
+        const int d = p.dir > 0 ? -1 : 1;
+        const int a = ti + (lane == 1 ? 0 : d), b = tj + (lane == 0 ? 0 : d);
+        if (lane < 3 && a >= 0 && a < p.nti && b >= 0 && b < p.ntj)
+            dep = (tk * p.ntj + b) * p.nti + a;
+        self = (tk * p.ntj + tj) * p.nti + ti;
+    }
+
+    // Plane k of an input array.  MODE_COMP: a halo plane that belongs to
+    // another k chunk comes from the copy taken before the pass (its owner
+    // may already have overwritten it); block boundary b (plane 1 + b*kchunk,
+    // b >= 1) has planes [Kb - shift, Kb + shift] at copy slot b - 1.
+    auto plane_base = [&](const real *src, int k) -> const real * {
+        const int kc = min(max(k, 0), p.nz + 1);
+        if constexpr (MODE == MODE_COMP) {
+            if (kc >= 1 && kc <= p.nz && (kc < k0 || kc >= k1)) {
+                const int kb = kc < k0 ? k0 : k1;
+                const int64_t slot = (kb - 1) / p.kchunk - 1;
+                return p.snap + (slot * (2 * p.shift + 1) + (kc - kb + p.shift)) * p.sz;
+            }
+        }
+        return src + (int64_t)kc * p.sz;
+    };
     auto load_plane = [&](const real *__restrict__ src, int k, real(&v)[R][CI]) {
-        const real *plane = src + (int64_t)min(max(k, 0), p.nz + 1) * p.sz;
+        const real *plane = plane_base(src, k);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const real *row = plane + rowoff[r];
@@ -245,6 +273,41 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
     // delivered this step), cur = plane k of level 0, nxt = prefetch of k+1.
     auto step = [&](int k, real(&Qi)[TL][R][CI], real(&Qo)[TL][R][CI], real(&cur)[R][CI],
                     real(&nxt)[R][CI]) {
+        if constexpr (MODE == MODE_COMP) {
+            // Every load issued so far has returned (plane k included), which
+            // the progress published after this step's barrier relies on.
+            // Before this step overwrites plane k - depth, the blocks that
+            // read it must have read it: progress > k - depth.  The poll
+            // issued last step usually says so; else wait (bounded).
+            __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+            got = max(got, pend);
+            const int wplane = k - depth;
+            if (wplane >= k0 && wplane < k1) {
+                const int need = wplane + 1;
+                if (!__all(dep < 0 || got >= need)) {
+                    int spins = 0;
+                    for (;;) {
+                        if (dep >= 0)
+                            got = __hip_atomic_load(p.prog + dep, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                        if (__all(dep < 0 || got >= need))
+                            break;
+                        const int err = __builtin_amdgcn_readfirstlane(
+                            __hip_atomic_load(p.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        if (++spins > p.spin_limit || err) {
+                            if (lane == 0)
+                                __hip_atomic_store(p.error, 1, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+            if (dep >= 0)
+                pend = __hip_atomic_load(p.prog + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         load_plane(p.src, k + 1, nxt);
         if constexpr (MODE == MODE_RHS) {
 #pragma unroll
@@ -380,6 +443,11 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                 }
             }
         __syncthreads();
+        if constexpr (MODE == MODE_COMP) {
+            // every wave has passed its vmcnt(0) of this step: planes <= k read
+            if (threadIdx.x == 0)
+                __hip_atomic_store(p.prog + self, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         auto dprev = [&](int side, int s, int c) -> real {
             if constexpr (DBUF)
                 return xold[xidx(w, side, s, c, lane)];
@@ -448,6 +516,40 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
     const int tk = bid / (p.nti * p.ntj);
     const int k0 = 1 + tk * p.kchunk;
     tb_tile<real, TL, CI, R, W, MODE>(p, ti, tj, k0, min(k0 + p.kchunk, p.nz + 1), TL, xch);
+}
+
+// One pass of the compressed single grid (Sect. 1.2): src and dst are two
+// frames of one array, dst shifted by (-shift, -shift, 0) cells against src
+// (dir = +1) or by (+shift, +shift, 0) (dir = -1), shift >= the halo.  A
+// block then overwrites only inputs of itself and of its neighbours at -1
+// along i, j or both (dir = +1; at +1 for dir = -1) in the same k chunk:
+// every other block reads none of the cells it writes, and halo planes of
+// other k chunks come from copies (plane_base).  So each block waits, per
+// plane, until those three neighbours have read the plane it overwrites
+// (write after read; no block reads what another writes in the same pass).
+// Workgroups take tickets in order and a ticket's blocks depend only on
+// blocks of earlier tickets, held by running workgroups, so waits end.
+template <typename real, int TL, int CI, int R, int W>
+__global__ __launch_bounds__(64 * W) void compressed_kernel(TbArgs<real> p)
+{
+    extern __shared__ unsigned char smem_raw[];
+    real *xch = reinterpret_cast<real *>(smem_raw);
+    __shared__ int ticket_s;
+    if (threadIdx.x == 0)
+        ticket_s = atomicAdd(p.ticket, 1);
+    __syncthreads();
+    const int m = ticket_s;
+    const int nkc = (p.nz + p.kchunk - 1) / p.kchunk;
+    if (m >= p.nti * p.ntj * nkc)
+        return;  // more workgroups than blocks: nothing to do
+    int ti = m % p.nti, tj = (m / p.nti) % p.ntj;
+    const int tk = m / (p.nti * p.ntj);
+    if (p.dir < 0) {
+        ti = p.nti - 1 - ti;
+        tj = p.ntj - 1 - tj;
+    }
+    const int k0 = 1 + tk * p.kchunk;
+    tb_tile<real, TL, CI, R, W, MODE_COMP>(p, ti, tj, k0, min(k0 + p.kchunk, p.nz + 1), TL, xch);
 }
 
 // Batched pass over many grids (items of the plan).  In persistent mode each
@@ -582,6 +684,45 @@ static KernInfo batch_info(int cfg, int depth)
 {
 #define JAC_CFG(ID, CI, R, W) \
     case ID: return batch_info_depth<real, CI, R, W>(depth);
+    switch (cfg) {
+        JAC_TILE_MENU(JAC_CFG)
+    default: return KernInfo{nullptr, 0, 0};
+    }
+#undef JAC_CFG
+}
+
+// Compressed-grid instances exist for 64-wide blocks (CI = 1) only.
+template <typename real, int TL, int CI, int R, int W>
+static KernInfo comp_info_one()
+{
+    if constexpr (CI == 1)
+        return KernInfo{(const void *)compressed_kernel<real, TL, CI, R, W>,
+                        xch_bytes<real, TL, CI, W>(), 64 * W};
+    else
+        return KernInfo{nullptr, 0, 0};
+}
+
+template <typename real, int CI, int R, int W>
+static KernInfo comp_info_depth(int depth)
+{
+    switch (depth) {
+    case 1: return comp_info_one<real, 1, CI, R, W>();
+    case 2: return comp_info_one<real, 2, CI, R, W>();
+    case 3: return comp_info_one<real, 3, CI, R, W>();
+    case 4: return comp_info_one<real, 4, CI, R, W>();
+    case 5: return comp_info_one<real, 5, CI, R, W>();
+    case 6: return comp_info_one<real, 6, CI, R, W>();
+    case 7: return comp_info_one<real, 7, CI, R, W>();
+    case 8: return comp_info_one<real, 8, CI, R, W>();
+    default: return KernInfo{nullptr, 0, 0};
+    }
+}
+
+template <typename real>
+static KernInfo comp_info(int cfg, int depth)
+{
+#define JAC_CFG(ID, CI, R, W) \
+    case ID: return comp_info_depth<real, CI, R, W>(depth);
     switch (cfg) {
         JAC_TILE_MENU(JAC_CFG)
     default: return KernInfo{nullptr, 0, 0};

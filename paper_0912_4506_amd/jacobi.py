@@ -286,6 +286,75 @@ def pipelined(a, b, T, team=4, t=1, bx=0, by=0, kchunk=0, waves=0):
     return PipelinePlan(a, b, T, team, t, bx, by, kchunk, waves).run("relaxed").results()[0]
 
 
+def compressed_shape(nx, ny, nz, t):
+    """Shape (nz+2, ny+2+t, nx+2+t) of a compressed-grid array for depth t."""
+    return (nz + 2, ny + 2 + t, nx + 2 + t)
+
+
+def compressed_frame(u, t, frame):
+    """View of frame 0 (cell (i, j, k) at u[k, j+t, i+t]) or frame 1 (at
+    u[k, j, i]) of a compressed-grid array u, shaped like a grid."""
+    if u.dim() != 3:
+        raise ValueError("a compressed-grid array is 3-D")
+    ny, nx = u.shape[1] - 2 - t, u.shape[2] - 2 - t
+    if ny < 1 or nx < 1:
+        raise ValueError(f"array {tuple(u.shape)} is too small for depth t = {t}")
+    return u[:, t:, t:] if frame == 0 else u[:, :ny + 2, :nx + 2]
+
+
+def compressed_grid(u, t):
+    """jac_grid_t of a compressed-grid array (interior and array strides)."""
+    if u.dim() != 3 or u.stride(2) != 1:
+        raise ValueError("a compressed-grid array is 3-D and contiguous along i")
+    nz, ny, nx = u.shape[0] - 2, u.shape[1] - 2 - t, u.shape[2] - 2 - t
+    return Grid(nx, ny, nz, u.stride(1), u.stride(0))
+
+
+class Compressed:
+    """T sweeps in one array (jacobi_compressed): u has compressed_shape()
+    and holds level 0 in frame 0.  run() enqueues the passes (no host copies,
+    no allocation); result() is the view of the frame holding level T."""
+
+    def __init__(self, u, T, t, bx=0, by=0, kchunk=0, waves=0):
+        if u.dtype not in _DTYPES:
+            raise TypeError(f"grids must be float32 or float64, got {u.dtype}")
+        self.u, self.T, self.t = u, int(T), int(t)
+        self.g = compressed_grid(u, self.t)
+        self.tile = _tile(t, bx, by, kchunk, waves)
+        lib = _lib.load()
+        nbytes = lib.jacobi_compressed_workspace(_DTYPES[u.dtype], ctypes.byref(self.g), self.T,
+                                                 ctypes.byref(self.tile))
+        if nbytes == 0:
+            check(_lib.JAC_EARG)
+        self.ws = torch.zeros(nbytes + 256, dtype=torch.uint8, device=u.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off:off + nbytes]
+        self.frame = 0
+
+    def run(self):
+        out = ctypes.c_int(0)
+        with torch.cuda.device(self.u.device):
+            check(_lib.load().jacobi_compressed(
+                _DTYPES[self.u.dtype], ctypes.byref(self.g), _ptr(self.u), self.T,
+                ctypes.byref(self.tile), _ptr(self.ws_view), self.ws_view.numel(), _stream(self.u),
+                ctypes.byref(out)))
+        self.frame = out.value
+        return self
+
+    def result(self):
+        return compressed_frame(self.u, self.t, self.frame)
+
+    def wait_error(self):
+        """True if a wait gave up (read after synchronising)."""
+        return bool(self.ws_view[:4].view(torch.int32).item())
+
+
+def compressed(u, T, t, bx=0, by=0, kchunk=0, waves=0):
+    """Level T of the grid in frame 0 of u, computed in place; returns the
+    view of the frame that holds it."""
+    return Compressed(u, T, t, bx, by, kchunk, waves).run().result()
+
+
 def batched(grids_a, grids_b, Ts, t=None, bx=0, by=0, kchunk=0, mode="relaxed", waves=0):
     """Level T[m] of every grid m (one launch); returns the result tensors."""
     return BatchPlan(grids_a, grids_b, Ts, t, bx, by, kchunk, waves).run(mode).results()

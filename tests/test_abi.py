@@ -131,3 +131,41 @@ def test_residual_and_copy_checks(lib):
                                           None) == JAC_EARG             # norm2 inside r32
     assert lib.jacobi_copy(A, P((1 << 20) + 16), 64, None) == JAC_EARG   # overlap
     assert lib.jacobi_copy(A, B, 12, None) == JAC_EARG                   # not a multiple of 16
+
+
+def test_compressed_checks(lib):
+    """jacobi_compressed: the frame shift is t, so t is required; the array
+    strides must leave room for both frames; 64-wide blocks only."""
+    g = Grid(40, 30, 20, 0, 0)
+    ws_need = lib.jacobi_compressed_workspace(1, ctypes.byref(g), 10, ctypes.byref(Tile(4, 0, 0, 0, 0)))
+    assert ws_need > 0
+    # the saved shell and the per-pass counters are always there; plane copies
+    # only with several k chunks
+    one_chunk = lib.jacobi_compressed_workspace(1, ctypes.byref(g), 10,
+                                                ctypes.byref(Tile(4, 0, 0, 20, 0)))
+    two_chunks = lib.jacobi_compressed_workspace(1, ctypes.byref(g), 10,
+                                                 ctypes.byref(Tile(4, 0, 0, 10, 0)))
+    assert two_chunks - one_chunk >= 9 * 46 * 36 * 8   # 2t+1 planes of the padded array
+    WS = P(1 << 34)
+    out = ctypes.c_int(7)
+
+    def call(g=g, u=A, T=10, tile=Tile(4, 0, 0, 0, 0), ws=WS, nbytes=ws_need, dtype=1, outp=True):
+        return lib.jacobi_compressed(dtype, ctypes.byref(g), u, T, ctypes.byref(tile), ws, nbytes,
+                                     None, ctypes.byref(out) if outp else None)
+
+    assert lib.jacobi_compressed_workspace(1, ctypes.byref(g), 10, ctypes.byref(Tile())) == 0
+    assert "tile->t" in err(lib)
+    assert call(tile=Tile(0, 0, 0, 0, 0)) == JAC_EARG and "t in 1.." in err(lib)
+    assert call(tile=Tile(9, 0, 0, 0, 0)) == JAC_EARG
+    assert call(g=Grid(40, 30, 20, 43, 0)) == JAC_EARG and "nx+2+t" in err(lib)
+    assert call(g=Grid(40, 30, 20, 46, 46 * 35)) == JAC_EARG and "ny+2+t" in err(lib)
+    assert call(tile=Tile(4, 128, 32, 0, 0)) == JAC_EUNSUPPORTED and "64-wide" in err(lib)
+    assert call(tile=Tile(4, 0, 0, 3, 0)) == JAC_EARG and "kchunk" in err(lib)
+    assert call(T=-1) == JAC_EARG
+    assert call(u=None) == JAC_EARG and "u is NULL" in err(lib)
+    assert call(ws=None) == JAC_EWORKSPACE
+    assert call(nbytes=ws_need - 1) == JAC_EWORKSPACE
+    assert call(ws=P((1 << 34) + 8)) == JAC_EARG and "256-byte" in err(lib)
+    assert call(ws=P((1 << 20) + 256)) == JAC_EARG and "overlaps" in err(lib)
+    assert call(outp=False) == JAC_EARG and "out_frame" in err(lib)
+    assert call(T=0) == 0 and out.value == 0          # nothing enqueued
