@@ -19,7 +19,7 @@ Other workloads (--workload): `batched` (64 grids, edges log-uniform in
 [32, 256], T = 50, one persistent launch), `adjoint` (256^3, T = 32, t = 8,
 forward + backward), `refine` (768^3 Laplace solve, FP32 inner / FP64 outer,
 vs all-FP64 Jacobi; runs many minutes), `pipelined` (512^3, T = 100, by the
-pipelined schedule).
+pipelined schedule), `compressed` (512^3, T = 100, in one array).
 """
 import argparse
 import json
@@ -330,6 +330,58 @@ def bench_pipelined(args):
             "plain_glups": round(lups / (pms * 1e-3) / 1e9, 1), "candidates": rows}
 
 
+def bench_compressed(args):
+    """512^3 FP64, T = 100 in one array (the compressed grid) at depths 4, 5
+    and 6 with the library's default block for each (--t pins one), against
+    jacobi_tblock with the same blocking on two arrays.  Each step runs from
+    frame 0 again (the work does not depend on the values)."""
+    import torch
+    from paper_0912_4506_amd import inputs, jacobi as jac
+
+    N, T = 512, 100
+    u = inputs.grid(N, N, N, seed=0)
+    lups = N ** 3 * T
+    rows = []
+    for t in ([args.t] if args.t else [4, 5, 6]):
+        d = jac.default_tile((N + 2,) * 3, T, t)
+        bx, by, w = (args.bx, args.by, args.waves) if args.bx else (d[1], d[2], d[4])
+        arr = torch.empty(jac.compressed_shape(N, N, N, t), dtype=torch.float64, device="cuda")
+        jac.compressed_frame(arr, t, 0).copy_(torch.from_numpy(u))
+        run = jac.Compressed(arr, T, t, bx=bx, by=by, waves=w)
+        ms = time_steps(run.run, args.steps, args.warmup)
+        torch.cuda.synchronize()
+        if run.wait_error():
+            raise RuntimeError("a compressed-grid wait gave up")
+        comp_bytes = arr.numel() * 8 + run.ws_view.numel()
+        del arr, run
+        torch.cuda.empty_cache()
+        a = torch.from_numpy(u).to("cuda")
+        b = torch.empty_like(a)
+        bms = time_steps(lambda: jac.tblock(a, b, T, t=t, bx=bx, by=by, waves=w), args.steps, 1)
+        del a, b
+        torch.cuda.empty_cache()
+        rows.append({"t": t, "tile_bx_by": [bx, by], "waves": w, "ms_per_step": round(ms, 3),
+                     "glups": round(lups / (ms * 1e-3) / 1e9, 2),
+                     "two_grid_tblock_glups": round(lups / (bms * 1e-3) / 1e9, 2),
+                     "memory_gb": round(comp_bytes / 1e9, 3), "passes": math.ceil(T / t)})
+        print(f"  t {t}: {rows[-1]['glups']} GLUP/s in one array, "
+              f"{rows[-1]['two_grid_tblock_glups']} in two", file=sys.stderr, flush=True)
+    best = max(rows, key=lambda r: r["glups"])
+    achieved = 16 * N ** 3 / (best["ms_per_step"] / best["passes"] * 1e-3) / 1e9
+    return {"metric": "GLUP/s, 512^3 FP64 Jacobi T=100, compressed single grid", "unit": "GLUP/s",
+            "value": best["glups"], "higher_is_better": True, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms_per_step"],
+            "dtype": "f64", "data": "synthetic: uniform [0,1) interior and shell, numpy default_rng(0)",
+            "config": {"workload": "jacobi3d 512^3 interior, FP64, T=100, one array",
+                       **{k: best[k] for k in ("t", "tile_bx_by", "waves", "passes")}},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "note": "per pass incl. its plane copies and shell rewrite"},
+            "memory_gb": {"compressed": best["memory_gb"],
+                          "two_grids": round(2 * 514 ** 3 * 8 / 1e9, 3)},
+            "by_depth": rows}
+
+
 def bench_refine(args):
     """Laplace solve to a relative FP64 residual of 1e-10 from a zero interior:
     FP64 refinement around FP32 blocked inner sweeps (50 per outer iteration)
@@ -411,7 +463,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="metric",
-                    choices=["metric", "batched", "adjoint", "refine", "pipelined"])
+                    choices=["metric", "batched", "adjoint", "refine", "pipelined", "compressed"])
     ap.add_argument("--autotune", action="store_true",
                     help="let the library's autotuner pick the blocking first")
     ap.add_argument("--tmax", type=int, default=8, help="deepest blocking depth the autotuner tries")
@@ -442,7 +494,8 @@ def main():
         sys.exit(2)
     ensure_built()
     fn = {"metric": bench_metric, "batched": bench_batched, "adjoint": bench_adjoint,
-          "refine": bench_refine, "pipelined": bench_pipelined}[args.workload]
+          "refine": bench_refine, "pipelined": bench_pipelined,
+          "compressed": bench_compressed}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

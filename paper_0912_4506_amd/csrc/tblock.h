@@ -123,15 +123,16 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
         fix_j = fix_j || sh_j[r];
     }
 
-    // MODE_COMP: lanes 0..2 name the blocks of the same k chunk whose inputs
-    // this block's output overwrites (the neighbours at -1 along i, j and
-    // both for dir = +1, at +1 for dir = -1), and follow their progress.
+    // MODE_COMP: lanes 0..2 of wave 0 name the blocks of the same k chunk
+    // whose inputs this block's output overwrites (the neighbours at -1 along
+    // i, j and both for dir = +1, at +1 for dir = -1), and follow their
+    // progress.
     int dep = -1, got = 0, pend = 0, self = 0;
     if constexpr (MODE == MODE_COMP) {
         const int tk = (k0 - 1) / p.kchunk;
         const int d = p.dir > 0 ? -1 : 1;
         const int a = ti + (lane == 1 ? 0 : d), b = tj + (lane == 0 ? 0 : d);
-        if (lane < 3 && a >= 0 && a < p.nti && b >= 0 && b < p.ntj)
+        if (w == 0 && lane < 3 && a >= 0 && a < p.nti && b >= 0 && b < p.ntj)
             dep = (tk * p.ntj + b) * p.nti + a;
         self = (tk * p.ntj + tj) * p.nti + ti;
     }
@@ -274,39 +275,51 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
     auto step = [&](int k, real(&Qi)[TL][R][CI], real(&Qo)[TL][R][CI], real(&cur)[R][CI],
                     real(&nxt)[R][CI]) {
         if constexpr (MODE == MODE_COMP) {
-            // Every load issued so far has returned (plane k included), which
-            // the progress published after this step's barrier relies on.
-            // Before this step overwrites plane k - depth, the blocks that
-            // read it must have read it: progress > k - depth.  The poll
-            // issued last step usually says so; else wait (bounded).
+            // Every load this wave issued has returned (plane k included).
+            // The last barrier followed the same wait of every wave one step
+            // earlier, so all waves have read planes < k: publish k.  (The
+            // counter store writes through to memory; issued here, its
+            // latency overlaps this step.)
             __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
-            got = max(got, pend);
-            const int wplane = k - depth;
-            if (wplane >= k0 && wplane < k1) {
-                const int need = wplane + 1;
-                if (!__all(dep < 0 || got >= need)) {
-                    int spins = 0;
-                    for (;;) {
-                        if (dep >= 0)
-                            got = __hip_atomic_load(p.prog + dep, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-                        if (__all(dep < 0 || got >= need))
-                            break;
-                        const int err = __builtin_amdgcn_readfirstlane(
-                            __hip_atomic_load(p.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                        if (++spins > p.spin_limit || err) {
-                            if (lane == 0)
-                                __hip_atomic_store(p.error, 1, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                            break;
+            if (threadIdx.x == 0 && k > kstart)
+                __hip_atomic_store(p.prog + self, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // Wave 0 clears the next step's writes: before any wave overwrites
+            // plane k + 1 - depth (after this step's barrier), the blocks that
+            // read it must have read it, i.e. their progress > k + 1 - depth.
+            // Polls are lazy: one answers for several steps while the
+            // neighbours keep pace, and the next is issued two steps before
+            // its answer is needed, so its latency overlaps this step (a
+            // counter poll reads memory, several microseconds under load).
+            if (w == 0) {
+                got = max(got, pend);
+                const int wplane = k + 1 - depth;
+                if (wplane >= k0 && wplane < k1) {
+                    const int need = wplane + 1;
+                    if (!__all(dep < 0 || got >= need)) {
+                        int spins = 0;
+                        for (;;) {
+                            if (dep >= 0)
+                                got = __hip_atomic_load(p.prog + dep, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                            if (__all(dep < 0 || got >= need))
+                                break;
+                            const int err = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                p.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                            if (++spins > p.spin_limit || err) {
+                                if (lane == 0)
+                                    __hip_atomic_store(p.error, 1, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
                         }
-                        __builtin_amdgcn_s_sleep(1);
                     }
+                    const bool stale = !__all(dep < 0 || got >= need + 2);
+                    if (stale && dep >= 0)
+                        pend = __hip_atomic_load(p.prog + dep, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
-            if (dep >= 0)
-                pend = __hip_atomic_load(p.prog + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         load_plane(p.src, k + 1, nxt);
         if constexpr (MODE == MODE_RHS) {
@@ -443,11 +456,6 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                 }
             }
         __syncthreads();
-        if constexpr (MODE == MODE_COMP) {
-            // every wave has passed its vmcnt(0) of this step: planes <= k read
-            if (threadIdx.x == 0)
-                __hip_atomic_store(p.prog + self, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
         auto dprev = [&](int side, int s, int c) -> real {
             if constexpr (DBUF)
                 return xold[xidx(w, side, s, c, lane)];
@@ -498,6 +506,12 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
             for (int c = 0; c < CI; ++c)
                 CA[r][c] = CB[r][c];
     }
+    if constexpr (MODE == MODE_COMP) {
+        // done: every plane this block reads has been read
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(p.prog + self, 1 << 30, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // One pass over a whole grid: workgroup (ti, tj, tk) streams output planes
@@ -532,7 +546,8 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
 template <typename real, int TL, int CI, int R, int W>
 __global__ __launch_bounds__(64 * W) void compressed_kernel(TbArgs<real> p)
 {
-    extern __shared__ unsigned char smem_raw[];
+    // dynamic LDS follows the static ticket_s: align it for 8-byte accesses
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     real *xch = reinterpret_cast<real *>(smem_raw);
     __shared__ int ticket_s;
     if (threadIdx.x == 0)
@@ -565,7 +580,7 @@ __global__ __launch_bounds__(64 * W) void compressed_kernel(TbArgs<real> p)
 template <typename real, int TL, int CI, int R, int W>
 __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     real *xch = reinterpret_cast<real *>(smem_raw);
     __shared__ int item_s, stop_s;
     int it = L.begin + (int)blockIdx.x;

@@ -7,8 +7,9 @@ benchmark times.
   one from their domain of dependence.  The samples include the shell
   corners, the edges of the blocks and k chunks the default plan uses, and
   random interior cells.
-* The same 512^3 grid by the pipelined schedule (bitwise) and in FP32 at the
-  default blocking (within 1e-5 of the oracle on the FP32-rounded input).
+* The same 512^3 grid by the pipelined schedule and in one array (the
+  compressed grid), bitwise, and in FP32 at the default blocking (within 1e-5
+  of the oracle on the FP32-rounded input).
 * 768^3, the refinement's inner solve: 50 FP32 sweeps with a right-hand side
   at the library's default depth against the oracle's full FP64 run, and the
   FP64 residual and the fused update-and-residual bitwise over the whole grid.
@@ -97,6 +98,18 @@ def test_512_pipelined_sampled(jac, grid512):
     out = jac.pipelined(a, b, T, team=2, t=4, kchunk=32)
     torch.cuda.synchronize()
     assert np.array_equal(sampled(out, pts), ref)
+
+
+def test_512_compressed_sampled(jac, grid512):
+    """The compressed single grid at the workload size (t = 4, the default
+    block), bitwise at the sampled cells of the frame holding level T."""
+    u, pts, ref = grid512
+    arr = torch.empty(jac.compressed_shape(N, N, N, 4), dtype=torch.float64, device="cuda")
+    jac.compressed_frame(arr, 4, 0).copy_(torch.from_numpy(u))
+    run = jac.Compressed(arr, T, 4).run()
+    torch.cuda.synchronize()
+    assert not run.wait_error()
+    assert np.array_equal(sampled(run.result(), pts), ref)
 
 
 @pytest.fixture(scope="module")
