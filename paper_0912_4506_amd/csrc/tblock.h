@@ -287,7 +287,7 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
             // plane k + 1 - depth (after this step's barrier), the blocks that
             // read it must have read it, i.e. their progress > k + 1 - depth.
             // Polls are lazy: one answers for several steps while the
-            // neighbours keep pace, and the next is issued two steps before
+            // neighbours keep pace, and the next is issued the step before
             // its answer is needed, so its latency overlaps this step (a
             // counter poll reads memory, several microseconds under load).
             if (w == 0) {
@@ -314,7 +314,7 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                             __builtin_amdgcn_s_sleep(1);
                         }
                     }
-                    const bool stale = !__all(dep < 0 || got >= need + 2);
+                    const bool stale = !__all(dep < 0 || got >= need + 1);
                     if (stale && dep >= 0)
                         pend = __hip_atomic_load(p.prog + dep, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
