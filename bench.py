@@ -37,6 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # 512^3 FP64 (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales the
 # 2 GiB copy gives; profiles/tblock_f64_t4_64x72_512cubed.md)
 MEASURED_TRAFFIC_GB = {(4, 64, 72, 12): 2.337}
+# the same for the compressed-grid kernel (profiles/compressed_f64_t5_512cubed.md)
+COMPRESSED_TRAFFIC_GB = {(5, 64, 56, 8): 2.627}
 METRIC = "GLUP/s & % roofline, 512³ FP64 Jacobi T=100: temporal-blocked vs plain"
 
 
@@ -375,7 +377,10 @@ def bench_compressed(args):
             "config": {"workload": "jacobi3d 512^3 interior, FP64, T=100, one array",
                        **{k: best[k] for k in ("t", "tile_bx_by", "waves", "passes")}},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": COMPRESSED_TRAFFIC_GB.get((best["t"], *best["tile_bx_by"],
+                                                               best["waves"])),
+                         "traffic_unit": "GB per launch",
                          "note": "per pass incl. its plane copies and shell rewrite"},
             "memory_gb": {"compressed": best["memory_gb"],
                           "two_grids": round(2 * 514 ** 3 * 8 / 1e9, 3)},
