@@ -384,6 +384,8 @@ int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, in
     const int dtype = sizeof(real) == 8 ? JAC_F64 : JAC_F32;
     const int P = (T + tile.t - 1) / tile.t;
     const DeviceFacts dev = device_facts();
+    if (g.sz * (int64_t)sizeof(real) >= jac::kDropOffset)
+        return fail(JAC_EUNSUPPORTED, "planes of 2 GiB or more are not supported by the blocked kernels");
     hipError_t e = jac::launch_copy_shell<real>(a, b, grid_args(g), st);
     if (e != hipSuccess)
         return hip_fail(e, "shell copy");
@@ -592,6 +594,8 @@ int plan_compressed(int dtype, const jac_grid_t *g, int T, const jac_tile_t *til
                     tl.by);
     if (tl.kchunk > 0 && tl.kchunk < S)
         return fail(JAC_EARG, "kchunk = %d is below t = %d", tl.kchunk, S);
+    if (geo->sz * (int64_t)elem_size(dtype) >= jac::kDropOffset)
+        return fail(JAC_EUNSUPPORTED, "planes of 2 GiB or more are not supported by the blocked kernels");
     CompPlan c;
     c.shape = shape;
     c.S = S;

@@ -45,6 +45,10 @@ struct PlainArgs {
     int64_t sy, sz;
 };
 
+// Byte offset the blocked kernels give a masked-off output store; planes
+// must be smaller (the host refuses planes of this many bytes or more).
+constexpr int kDropOffset = 0x7ffffff0;
+
 template <typename real>
 struct TbArgs {
     const real *src;

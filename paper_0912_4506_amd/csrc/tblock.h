@@ -275,12 +275,14 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
     auto step = [&](int k, real(&Qi)[TL][R][CI], real(&Qo)[TL][R][CI], real(&cur)[R][CI],
                     real(&nxt)[R][CI]) {
         if constexpr (MODE == MODE_COMP) {
-            // Every load this wave issued has returned (plane k included).
-            // The last barrier followed the same wait of every wave one step
-            // earlier, so all waves have read planes < k: publish k.  (The
-            // counter store writes through to memory; issued here, its
-            // latency overlaps this step.)
-            __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+            // Every load this wave issued has returned (plane k included):
+            // the only vector memory operations issued after plane k's loads
+            // are the previous step's R x CI output stores, and vmcnt counts
+            // in issue order.  The last barrier followed the same wait of
+            // every wave one step earlier, so all waves have read planes < k:
+            // publish k.  (The counter store writes through to memory; issued
+            // here, its latency overlaps this step.)
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(R * CI));
             if (threadIdx.x == 0 && k > kstart)
                 __hip_atomic_store(p.prog + self, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // Wave 0 clears the next step's writes: before any wave overwrites
@@ -399,21 +401,38 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                     for (int c = 0; c < CI; ++c)
                         Qo[s < TL ? s : 0][r][c] = o[r][c];
                 trace_level(s, plane, Qo[s < TL ? s : 0]);
-            } else if (plane >= k0 && plane < k1) {
-                real *dplane = p.dst + (int64_t)plane * p.sz;
+            } else if constexpr (MODE == MODE_BATCH) {
+                if (plane >= k0 && plane < k1) {
+                    real *dplane = p.dst + (int64_t)plane * p.sz;
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (ok_j[r]) {
-                        real *row = dplane + rowoff[r];
+                    for (int r = 0; r < R; ++r)
+                        if (ok_j[r]) {
+                            real *row = dplane + rowoff[r];
 #pragma unroll
-                        for (int c = 0; c < CI; ++c)
-                            if (ok_i[c]) {
-                                if constexpr (MODE == MODE_BATCH)
+                            for (int c = 0; c < CI; ++c)
+                                if (ok_i[c])
                                     __hip_atomic_store(&row[ic[c]], o[r][c], __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
-                                else
-                                    row[ic[c]] = o[r][c];
-                            }
+                        }
+                }
+            } else {
+                // The same R x CI stores on every step: cells outside the
+                // valid region get the drop offset, and a plane outside
+                // [k0, k1) a record count of 0.  vmcnt counts loads and stores
+                // in issue order, so with a fixed store count the wait for the
+                // next plane's loads at the end of the step no longer waits
+                // for these stores (it did when they sat behind branches).
+                const bool wr = plane >= k0 && plane < k1;
+                const auto rs = plane_rsrc(p.dst + (int64_t)(wr ? plane : 0) * p.sz,
+                                           wr ? (int)(p.sz * (int64_t)sizeof(real)) : 0);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < CI; ++c) {
+                        const int off = (ok_j[r] && ok_i[c])
+                                            ? (int)((rowoff[r] + ic[c]) * (int64_t)sizeof(real))
+                                            : kDropOffset;
+                        plane_store(o[r][c], rs, off);
                     }
             }
             // advance P[s-1] (rows 1 .. R-2) from the plane delivered to level s
