@@ -246,6 +246,8 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
 
     real CA[R][CI], CB[R][CI];
     load_plane(p.src, kstart, CA);
+    if constexpr (MODE == MODE_COMP)
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));  // the first plane is read (see step)
 
     const int wa = w > 0 ? w - 1 : w;      // wave holding row j-1 of row 0
     const int wb = w < W - 1 ? w + 1 : w;  // wave holding row j+1 of row R-1
