@@ -725,6 +725,8 @@ int jacobi_plain(int dtype, const jac_grid_t *g, void *a, void *b, int T, void *
     *out_idx = 0;
     if (T == 0)
         return JAC_OK;
+    if (geo.sz * (int64_t)elem_size(dtype) >= jac::kDropOffset)
+        return fail(JAC_EUNSUPPORTED, "planes of 2 GiB or more are not supported by the sweep kernels");
     hipStream_t st = (hipStream_t)stream;
     // k-chunk: long streams (contiguous reads), but enough blocks to fill the
     // chip (with 128-thread strips, two per CU)

@@ -80,7 +80,9 @@ __global__ __launch_bounds__(NT) void plain_kernel(const real *__restrict__ A,
     load(k0, cur, cw, ce);
     for (int k = k0; k < k1; ++k) {
         load(k + 1, nxt, nw, ne);
-        real *out = B + (int64_t)k * p.sz;
+        // the same 2 x RB stores every step (cells outside the grid get the
+        // drop offset), so the wait for the next plane skips the stores
+        const auto rs = plane_rsrc(B + (int64_t)k * p.sz, (int)(p.sz * (int64_t)sizeof(real)));
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             real s0 = cw[r] + cur[r + 1][1];
@@ -93,12 +95,14 @@ __global__ __launch_bounds__(NT) void plain_kernel(const real *__restrict__ A,
             s1 = s1 + cur[r + 2][1];
             s1 = s1 + prev[r][1];
             s1 = s1 + nxt[r + 1][1];
-            if (j0 + r <= p.ny) {
-                if (i0 <= p.nx)
-                    out[ro[r + 1] + i0] = div6(s0);
-                if (i0 + 1 <= p.nx)
-                    out[ro[r + 1] + i0 + 1] = div6(s1);
-            }
+            const bool row = j0 + r <= p.ny;
+            const int o0 = row && i0 <= p.nx ? (int)((ro[r + 1] + i0) * (int64_t)sizeof(real))
+                                             : kDropOffset;
+            const int o1 = row && i0 + 1 <= p.nx
+                               ? (int)((ro[r + 1] + i0 + 1) * (int64_t)sizeof(real))
+                               : kDropOffset;
+            plane_store(div6(s0), rs, o0);
+            plane_store(div6(s1), rs, o1);
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
