@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 # (t, bx, by, waves) -> measured HBM GB per launch of the blocked kernel at
 # 512^3 FP64 (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales the
 # 2 GiB copy gives; profiles/tblock_f64_t4_64x72_512cubed.md)
-MEASURED_TRAFFIC_GB = {(4, 64, 72, 12): 2.318}
+MEASURED_TRAFFIC_GB = {(4, 64, 72, 12): 2.317}
 # the same for the compressed-grid kernel (profiles/compressed_f64_t5_512cubed.md)
 COMPRESSED_TRAFFIC_GB = {(5, 64, 56, 8): 2.682}
 METRIC = "GLUP/s & % roofline, 512³ FP64 Jacobi T=100: temporal-blocked vs plain"
