@@ -261,7 +261,7 @@ int default_depth(int dtype, int kind)
 int kind_scratch(int dtype, int kind, int cfg, int depth)
 {
     if (kind == KIND_BATCH)
-        return jac::batched_scratch(dtype, cfg, depth);
+        return jac::batched_scratch(dtype, cfg, depth, 0);
     const int mode = kind == KIND_RHS ? jac::MODE_RHS : kind == KIND_TRACE ? jac::MODE_TRACE
                                                                           : jac::MODE_PLAIN;
     return jac::tblock_scratch(dtype, cfg, depth, mode);
@@ -1247,6 +1247,14 @@ int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws, si
     const jac::BatchGrid *grids = (const jac::BatchGrid *)(dimg + h.grids_off);
     const jac::BatchItem *items = (const jac::BatchItem *)(dimg + h.items_off);
     const int *pass_start = (const int *)((const unsigned char *)plan_host + h.pass_off);
+    // every item has the full depth when every grid's T is a multiple of t:
+    // then the kernel instance with the depth as a constant runs
+    const jac::BatchGrid *hgrids =
+        (const jac::BatchGrid *)((const unsigned char *)plan_host + h.grids_off);
+    int fixed = 1;
+    for (int m = 0; m < h.n; ++m)
+        if (hgrids[m].T != hgrids[m].passes * h.t)
+            fixed = 0;
     hipError_t e = h.dtype == JAC_F64 ? jac::launch_batch_shells<double>(grids, h.n, h.max_shell, st)
                                       : jac::launch_batch_shells<float>(grids, h.n, h.max_shell, st);
     if (e != hipSuccess)
@@ -1263,13 +1271,13 @@ int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws, si
         if ((e = jac::launch_zero_ints((int *)ws, h.ntiles + 2, st)) != hipSuccess)
             return hip_fail(e, "counter reset");
         const DeviceFacts dev = device_facts();
-        int occ = jac::batched_occupancy(h.dtype, h.cfg, h.t);
+        int occ = jac::batched_occupancy(h.dtype, h.cfg, h.t, fixed);
         if (occ < 1)
             occ = 1;
         L.begin = 0;
         L.end = h.nitems;
         L.persistent = 1;
-        e = jac::launch_batched(h.dtype, h.cfg, h.t, L, std::min(h.nitems, dev.cus * occ), st);
+        e = jac::launch_batched(h.dtype, h.cfg, h.t, fixed, L, std::min(h.nitems, dev.cus * occ), st);
         if (e != hipSuccess)
             return hip_fail(e, "batched launch");
     } else {
@@ -1278,7 +1286,7 @@ int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws, si
             L.end = pass_start[pass + 1];
             L.persistent = 0;
             if (L.end > L.begin &&
-                (e = jac::launch_batched(h.dtype, h.cfg, h.t, L, L.end - L.begin, st)) != hipSuccess)
+                (e = jac::launch_batched(h.dtype, h.cfg, h.t, fixed, L, L.end - L.begin, st)) != hipSuccess)
                 return hip_fail(e, "batched pass launch");
         }
     }

@@ -122,8 +122,9 @@ struct BatchItem {
 // Persistent (relaxed) mode: blocks pop items in order and wait for the
 // neighbouring blocks of the previous pass through per-block counters.
 // Lockstep mode: one launch per pass, one item per workgroup.
-KernInfo batch_info_f64(int cfg, int depth);
-KernInfo batch_info_f32(int cfg, int depth);
+// fixed = 1: the instance for launches whose items all have depth `depth`
+KernInfo batch_info_f64(int cfg, int depth, int fixed);
+KernInfo batch_info_f32(int cfg, int depth, int fixed);
 
 struct BatchLaunch {
     const BatchGrid *grids;
@@ -178,10 +179,10 @@ template <typename real>
 hipError_t launch_grid_fill(real *x, real v, const GridArgs &g, hipStream_t st);
 hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStream_t st);
 
-hipError_t launch_batched(int dtype, int cfg, int depth, const BatchLaunch &L, int nblocks,
+hipError_t launch_batched(int dtype, int cfg, int depth, int fixed, const BatchLaunch &L, int nblocks,
                           hipStream_t st);
-int batched_occupancy(int dtype, int cfg, int depth);
-int batched_scratch(int dtype, int cfg, int depth);
+int batched_occupancy(int dtype, int cfg, int depth, int fixed);
+int batched_scratch(int dtype, int cfg, int depth, int fixed);
 
 // Per-lane scratch (register spill) bytes of a tblock instance, -1 if none.
 int tblock_scratch(int dtype, int cfg, int depth, int mode);

@@ -546,10 +546,10 @@ hipError_t launch_tblock(int cfg, int depth, int mode, const TbArgs<real> &p, in
     return hipGetLastError();
 }
 
-hipError_t launch_batched(int dtype, int cfg, int depth, const BatchLaunch &L, int nblocks,
+hipError_t launch_batched(int dtype, int cfg, int depth, int fixed, const BatchLaunch &L, int nblocks,
                           hipStream_t st)
 {
-    const KernInfo ki = dtype == 1 ? batch_info_f64(cfg, depth) : batch_info_f32(cfg, depth);
+    const KernInfo ki = dtype == 1 ? batch_info_f64(cfg, depth, fixed) : batch_info_f32(cfg, depth, fixed);
     if (!ki.fn)
         return hipErrorInvalidValue;
     if (ki.lds > 65536) {
@@ -568,9 +568,9 @@ hipError_t launch_batched(int dtype, int cfg, int depth, const BatchLaunch &L, i
     return hipGetLastError();
 }
 
-int batched_scratch(int dtype, int cfg, int depth)
+int batched_scratch(int dtype, int cfg, int depth, int fixed)
 {
-    const KernInfo ki = dtype == 1 ? batch_info_f64(cfg, depth) : batch_info_f32(cfg, depth);
+    const KernInfo ki = dtype == 1 ? batch_info_f64(cfg, depth, fixed) : batch_info_f32(cfg, depth, fixed);
     if (!ki.fn)
         return -1;
     hipFuncAttributes attr;
@@ -579,9 +579,9 @@ int batched_scratch(int dtype, int cfg, int depth)
     return (int)attr.localSizeBytes;
 }
 
-int batched_occupancy(int dtype, int cfg, int depth)
+int batched_occupancy(int dtype, int cfg, int depth, int fixed)
 {
-    const KernInfo ki = dtype == 1 ? batch_info_f64(cfg, depth) : batch_info_f32(cfg, depth);
+    const KernInfo ki = dtype == 1 ? batch_info_f64(cfg, depth, fixed) : batch_info_f32(cfg, depth, fixed);
     if (!ki.fn)
         return 0;
     int n = 0;

@@ -3,9 +3,9 @@
 
 namespace jac {
 
-KernInfo batch_info_f32(int cfg, int depth)
+KernInfo batch_info_f32(int cfg, int depth, int fixed)
 {
-    return batch_info<float>(cfg, depth);
+    return batch_info<float>(cfg, depth, fixed);
 }
 
 }  // namespace jac

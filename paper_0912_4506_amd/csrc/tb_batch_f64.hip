@@ -3,9 +3,9 @@
 
 namespace jac {
 
-KernInfo batch_info_f64(int cfg, int depth)
+KernInfo batch_info_f64(int cfg, int depth, int fixed)
 {
-    return batch_info<double>(cfg, depth);
+    return batch_info<double>(cfg, depth, fixed);
 }
 
 }  // namespace jac

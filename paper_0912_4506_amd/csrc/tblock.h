@@ -598,7 +598,9 @@ __global__ __launch_bounds__(64 * W) void compressed_kernel(TbArgs<real> p)
 // Sect. 1.3 (Eq. 3), with a per-block counter in place of a per-thread one.
 // Items are handed out in pass order and a block waits only on items handed
 // out before its own, all held by running blocks, so the waits always end.
-template <typename real, int TL, int CI, int R, int W>
+// FIXED: every item of the launch has depth TL (all grids run T a multiple of
+// t); the depth is then a compile-time constant, which saves registers.
+template <typename real, int TL, int CI, int R, int W, bool FIXED>
 __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -676,8 +678,8 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
         p.kchunk = G.kchunk;
         const int depth = G.T / G.passes + (m.pass < G.T % G.passes ? 1 : 0);
         const int k0 = 1 + tk * G.kchunk;
-        tb_tile<real, TL, CI, R, W, MODE_BATCH>(p, ti, tj, k0, min(k0 + G.kchunk, G.nz + 1), depth,
-                                                xch);
+        tb_tile<real, TL, CI, R, W, MODE_BATCH>(p, ti, tj, k0, min(k0 + G.kchunk, G.nz + 1),
+                                                FIXED ? TL : depth, xch);
         if (!L.persistent)
             break;
         // Publish: the item's output stores are agent-scope, so they write
@@ -693,33 +695,34 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
 }
 
 template <typename real, int TL, int CI, int R, int W>
-static KernInfo batch_info_one()
+static KernInfo batch_info_one(int fixed)
 {
-    return KernInfo{(const void *)batched_kernel<real, TL, CI, R, W>, xch_bytes<real, TL, CI, W>(),
-                    64 * W};
+    const void *fn = fixed ? (const void *)batched_kernel<real, TL, CI, R, W, true>
+                           : (const void *)batched_kernel<real, TL, CI, R, W, false>;
+    return KernInfo{fn, xch_bytes<real, TL, CI, W>(), 64 * W};
 }
 
 template <typename real, int CI, int R, int W>
-static KernInfo batch_info_depth(int depth)
+static KernInfo batch_info_depth(int depth, int fixed)
 {
     switch (depth) {
-    case 1: return batch_info_one<real, 1, CI, R, W>();
-    case 2: return batch_info_one<real, 2, CI, R, W>();
-    case 3: return batch_info_one<real, 3, CI, R, W>();
-    case 4: return batch_info_one<real, 4, CI, R, W>();
-    case 5: return batch_info_one<real, 5, CI, R, W>();
-    case 6: return batch_info_one<real, 6, CI, R, W>();
-    case 7: return batch_info_one<real, 7, CI, R, W>();
-    case 8: return batch_info_one<real, 8, CI, R, W>();
+    case 1: return batch_info_one<real, 1, CI, R, W>(fixed);
+    case 2: return batch_info_one<real, 2, CI, R, W>(fixed);
+    case 3: return batch_info_one<real, 3, CI, R, W>(fixed);
+    case 4: return batch_info_one<real, 4, CI, R, W>(fixed);
+    case 5: return batch_info_one<real, 5, CI, R, W>(fixed);
+    case 6: return batch_info_one<real, 6, CI, R, W>(fixed);
+    case 7: return batch_info_one<real, 7, CI, R, W>(fixed);
+    case 8: return batch_info_one<real, 8, CI, R, W>(fixed);
     default: return KernInfo{nullptr, 0, 0};
     }
 }
 
 template <typename real>
-static KernInfo batch_info(int cfg, int depth)
+static KernInfo batch_info(int cfg, int depth, int fixed)
 {
 #define JAC_CFG(ID, CI, R, W) \
-    case ID: return batch_info_depth<real, CI, R, W>(depth);
+    case ID: return batch_info_depth<real, CI, R, W>(depth, fixed);
     switch (cfg) {
         JAC_TILE_MENU(JAC_CFG)
     default: return KernInfo{nullptr, 0, 0};
