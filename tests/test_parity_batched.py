@@ -35,6 +35,21 @@ def test_batched_bitwise(jac, mode, t, tile):
         assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T)), (m, mode, t, tile)
 
 
+@pytest.mark.parametrize("mode", ["relaxed", "lockstep"])
+@pytest.mark.parametrize("t,tile", [(3, (64, 64)), (5, (64, 60)), (8, (64, 48))])
+def test_batched_full_depth_instance(jac, mode, t, tile):
+    """Every T a multiple of t: every item has the full depth, and the run
+    uses the kernel instance whose depth is a constant."""
+    Ts = [t * q for q in (1, 4, 2, 7, 3, 5, 1)]
+    us, a, b = make_batch(SHAPES, seed=9)
+    plan = jac.BatchPlan(a, b, Ts, t=t, bx=tile[0], by=tile[1])
+    plan.run(mode)
+    torch.cuda.synchronize()
+    assert not plan.wait_error()
+    for m, (u, T, out) in enumerate(zip(us, Ts, plan.results())):
+        assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T)), (m, mode, t, tile)
+
+
 def test_batched_small_kchunk(jac):
     """Several k chunks per grid: dependencies between chunks of one pass."""
     us, a, b = make_batch([(70, 50, 90), (33, 33, 40)])
