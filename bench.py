@@ -40,6 +40,10 @@ MEASURED_TRAFFIC_GB = {(4, 64, 72, 12): 2.317}
 # the same for the compressed-grid kernel (profiles/compressed_f64_t5_512cubed.md)
 COMPRESSED_TRAFFIC_GB = {(5, 64, 56, 8): 2.682}
 METRIC = "GLUP/s & % roofline, 512³ FP64 Jacobi T=100: temporal-blocked vs plain"
+# why a depth the workload names has no kernel
+DEPTH_REFUSAL = {16: " (the blocked pass keeps about two values per cell and level in "
+                     "registers, 4t VGPRs per cell in FP64: depth 16 would need 64 per cell, and "
+                     "depth 8 already spills on blocks with useful halo overhead)"}
 
 
 def ensure_built():
@@ -141,19 +145,24 @@ def bench_metric(args):
 
     by_depth = {}
     if args.depths:
+        from paper_0912_4506_amd._lib import JacobiError
         for d in [int(x) for x in args.depths.split(",") if x]:
-            best = None
+            best, refusal = None, None
             for (sx, sy, sw) in jac.tile_menu(torch.float64):
                 try:
                     dms = time_steps(lambda: jac.tblock(state["a"], state["b"], T, t=d, bx=sx, by=sy,
                                                         waves=sw), 1, 1)
-                except Exception:
+                except JacobiError as e:
+                    refusal = str(e)
                     continue
                 if best is None or dms < best[0]:
                     best = (dms, sx, sy, sw)
             if best:
                 by_depth[str(d)] = {"glups": round(lups / (best[0] * 1e-3) / 1e9, 1),
                                     "tile": [best[1], best[2]], "waves": best[3]}
+            else:
+                by_depth[str(d)] = ("refused: " + (refusal or "no block shape runs at this depth")
+                                    + DEPTH_REFUSAL.get(d, ""))
 
     plain = None
     if not args.no_plain:
@@ -293,9 +302,14 @@ def bench_adjoint(args):
 
 def bench_pipelined(args):
     """512^3 FP64, T = 100 by pipelined temporal blocking (the team pipeline
-    with relaxed synchronisation, one persistent launch): the fastest of a
-    small set of (team, sweeps per item, k chunk) against the overlapped-tile
-    default and the plain kernel on the same grid."""
+    with relaxed synchronisation, one persistent launch).  Two parts:
+      * the looseness sweep of the paper's relaxed-synchronisation study
+        (Eq. 3): for a few (team, sweeps per item, k chunk) settings, the
+        upper distance du in {1 (lock-step with dl = 1), 2, 4, none} and a
+        team delay of 8 chunks;
+      * the fastest of a small grid of (team, sweeps per item, k chunk) with
+        no upper bound,
+    against the overlapped-tile default and the plain kernel on the same grid."""
     import torch
     from paper_0912_4506_amd import inputs, jacobi as jac
 
@@ -304,23 +318,40 @@ def bench_pipelined(args):
     a = torch.from_numpy(u).to("cuda")
     b = torch.empty_like(a)
     lups = N ** 3 * T
+
+    def measure(team, t, kc, dl=1, du=0, dt=0):
+        try:
+            plan = jac.PipelinePlan(a, b, T, team=team, t=t, kchunk=kc, dl=dl, du=du, dt=dt)
+        except Exception as e:          # a refused shape: skip it
+            print(f"  team {team} t {t} kchunk {kc}: {e}", file=sys.stderr)
+            return None
+        ms = time_steps(lambda: plan.run("relaxed"), max(1, args.steps // 2), 1)
+        if plan.wait_error():
+            raise RuntimeError("a relaxed-mode wait gave up")
+        row = {"team": team, "t": t, "kchunk": kc, "dl": dl, "du": du if du else "none", "dt": dt,
+               "glups": round(lups / (ms * 1e-3) / 1e9, 1)}
+        print(f"  {row}", file=sys.stderr, flush=True)
+        return row
+
+    looseness = []
+    for team, t, kc in ((4, 1, 16), (8, 1, 32), (4, 2, 32), (4, 4, 64)):
+        rows = [measure(team, t, kc, 1, du) for du in (1, 2, 4, 0)]
+        rows.append(measure(team, t, kc, 1, 2, 8))
+        rows = [r for r in rows if r]
+        if rows:
+            lock = rows[0]["glups"] if rows[0]["du"] == 1 else None
+            looseness.append({"team": team, "t": t, "kchunk": kc,
+                              "glups_by_du": {str(r["du"]): r["glups"] for r in rows if r["dt"] == 0},
+                              "glups_du2_dt8": next((r["glups"] for r in rows if r["dt"] == 8), None),
+                              "best_vs_lockstep": round(max(r["glups"] for r in rows) / lock, 3)
+                              if lock else None})
     rows = []
     for team in (1, 2, 4, 8):
         for t in (1, 2, 4):
             for kc in (16, 32, 64, 128):
-                try:
-                    plan = jac.PipelinePlan(a, b, T, team=team, t=t, kchunk=kc)
-                except Exception as e:          # a refused shape: skip it
-                    print(f"  team {team} t {t} kchunk {kc}: {e}", file=sys.stderr)
-                    continue
-                ms = time_steps(lambda: plan.run("relaxed"), max(1, args.steps // 2), 1)
-                if plan.wait_error():
-                    raise RuntimeError("a relaxed-mode wait gave up")
-                rows.append({"team": team, "t": t, "kchunk": kc,
-                             "glups": round(lups / (ms * 1e-3) / 1e9, 1)})
-                print(f"  team {team} t {t} kchunk {kc}: {rows[-1]['glups']} GLUP/s", file=sys.stderr,
-                      flush=True)
-                del plan
+                r = measure(team, t, kc)
+                if r:
+                    rows.append(r)
     best = max(rows, key=lambda r: r["glups"])
     bms = time_steps(lambda: jac.tblock(a, b, T), args.steps, 1)
     pms = time_steps(lambda: jac.plain(a, b, T), max(1, args.steps // 2), 1)
@@ -329,7 +360,8 @@ def bench_pipelined(args):
             "data": "synthetic: uniform [0,1) interior and shell, numpy default_rng(0)",
             "config": {"workload": "jacobi3d 512^3 interior, FP64, T=100", **best},
             "overlapped_tiles_glups": round(lups / (bms * 1e-3) / 1e9, 1),
-            "plain_glups": round(lups / (pms * 1e-3) / 1e9, 1), "candidates": rows}
+            "plain_glups": round(lups / (pms * 1e-3) / 1e9, 1),
+            "looseness": looseness, "candidates": rows}
 
 
 def bench_compressed(args):
@@ -476,7 +508,7 @@ def main():
     ap.add_argument("--bx", type=int, default=0, help="pin the block shape (with --t)")
     ap.add_argument("--by", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
-    ap.add_argument("--depths", default="1,2,3,4,5,6,8",
+    ap.add_argument("--depths", default="1,2,3,4,5,6,8,16",
                     help="depths reported in by_depth (best block shape each)")
     ap.add_argument("--traffic", default=None,
                     help="measured HBM GB per blocked launch to report as roofline.traffic")

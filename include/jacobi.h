@@ -22,10 +22,24 @@
  *    corners of the shell are never read.
  *  - dtype: JAC_F32 (float) or JAC_F64 (double); all grids of a call share it.
  *  - Arithmetic: FP64 sums the six neighbours left to right in the printed
- *    order (i-1, i+1, j-1, j+1, k-1, k+1) and divides by 6 with a correctly
- *    rounded division, so every FP64 result is bitwise the plain sequential
- *    result, whatever the blocking depth, tile or pass split.  FP32 sums in
- *    the same order and multiplies by the float nearest 1/6.
+ *    order (i-1, i+1, j-1, j+1, k-1, k+1) and divides by 6.  jacobi_plain and
+ *    the adjoint's shell-face gradient divide exactly as IEEE division does,
+ *    for every input (infinities, NaN, subnormals and signed zeros included).
+ *    The temporally blocked passes (jacobi_tblock, the adjoint's interior,
+ *    batched, pipelined and compressed runs) divide in three operations whose
+ *    result is the IEEE quotient whenever that quotient is zero (of either
+ *    sign) or a normal number: so wherever every sum is finite and every
+ *    nonzero quotient is at least 2^-1022 in magnitude, each FP64 result is
+ *    bitwise the plain sequential result, whatever the blocking depth, tile
+ *    or pass split.  Outside that range the blocked passes differ from IEEE
+ *    division in two ways only: a sum of +-Inf gives NaN instead of +-Inf
+ *    (so the cells that the oracle makes infinite hold NaN or the same
+ *    infinity, and every finite cell is bitwise), and a quotient in the
+ *    subnormal range may be one subnormal step (2^-1074) off, a difference
+ *    later levels carry along (at most about 2 steps per level).  (Checking
+ *    every quotient costs one more vector instruction per cell and level in
+ *    the blocked pass, about 7% more, and the branch to redo it registers.)
+ *    FP32 sums in the same order and multiplies by the float nearest 1/6.
  *  - Calls enqueue work on `stream` (a hipStream_t; NULL = the null stream)
  *    and return without synchronising.  Argument checks happen before any
  *    HIP call and are synchronous: a failed check returns JAC_EARG and
@@ -52,7 +66,7 @@
 extern "C" {
 #endif
 
-#define JACOBI_ABI_VERSION 1
+#define JACOBI_ABI_VERSION 2
 
 /* Grid geometry.  nx, ny, nz >= 1 are the interior extents.  sy and sz are the
  * element strides of j and k; 0 selects the dense strides sy = nx+2 and
@@ -112,7 +126,7 @@ int jacobi_plain(int dtype, const jac_grid_t *g, void *a, void *b, int T,
  * (6I - adjacency) e = rhs; rhs is a grid of the same dtype and geometry
  * (shell ignored), read-only, not overlapping a or b.  The rhs term is added
  * after the six neighbours, so FP64 results stay bitwise those of the plain
- * sequential iteration. */
+ * sequential iteration (within the range stated under Arithmetic above). */
 int jacobi_tblock(int dtype, const jac_grid_t *g, void *a, void *b, int T,
                   const jac_tile_t *tile, const void *rhs, void *stream,
                   int *out_idx);
@@ -171,29 +185,46 @@ size_t jacobi_batched_workspace(const void *plan_host);
 int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws,
                        size_t ws_bytes, int mode, void *stream);
 
-/* Pipelined temporal blocking of one grid: the team pipeline of Sect. 1.2 with
- * the relaxed synchronisation of Sect. 1.3 (the lower bound of Eq. 3), in GPU
+/* Pipelined temporal blocking of one grid: the team pipeline of Sect. 1.3 with
+ * the relaxed synchronisation of Sect. 1.3 (both conditions of Eq. 3), in GPU
  * form.  T sweeps are cut into passes of tile->t sweeps (t = 0: 1 sweep per
  * item); each item runs one pass on one block of k chunk q (tile->kchunk
- * planes, 0: 16) and waits for the 27 neighbouring blocks of the previous
- * pass.  Consecutive passes form segments of `team` passes (1..1024); within
- * a segment the items go out in wavefronts, pass p on chunk q beside pass p+1
- * on chunk q-1, so the passes of a segment stream through the grid one chunk
- * apart, as the threads of a team follow each other through the blocks of a
- * shared cache.  No cell is computed more often than with tile->t sweeps per
- * block (no halo is recomputed when t = 1).  The plan image has the layout of
- * a one-grid batch: size it with jacobi_pipelined_plan_bytes, copy it to the
- * device, size the workspace with jacobi_batched_workspace and run it with
- * jacobi_batched_run in JAC_BATCH_RELAXED mode (lockstep is refused, JAC_EARG).
- * a, b, out_idx_host and the errors are as for jacobi_batched_plan with n = 1. */
+ * planes, 0: 16).  Consecutive passes form segments of `team` passes
+ * (1..1024), the GPU analog of a thread team: within a segment the items go
+ * out in wavefronts, pass p on chunk q beside pass p+1 on chunk q - dl - 1,
+ * so the passes of a segment stream through the grid a few chunks apart, as
+ * the threads of a team follow each other through the blocks of a shared
+ * cache; segments follow each other.  No cell is computed more often than
+ * with tile->t sweeps per block (no halo is recomputed when t = 1).
+ * Synchronisation (one counter per block; distances in k chunks, counted
+ * beyond the one chunk of halo a pass needs from the pass before it; c_p =
+ * chunks pass p has finished in a block column):
+ *   c_{p-1} - c_p >= dl + 1  (lower bound: the data the item reads, plus
+ *                            dl - 1 chunks of slack; dl >= 1),
+ *   c_p - c_{p+1} <= du + 1  (upper bound, the pipeline's looseness; du = 0:
+ *                            none, else du >= dl; dl = du = 1 is the paper's
+ *                            lock-step case),
+ * and a segment's front pass keeps dl + dt from the previous segment (dt,
+ * the team delay, >= 0); the first pass has no lower and a segment's last
+ * pass no upper condition.  sync == NULL: dl = 1, du = 0, dt = 0.  The
+ * items also wait for the 27 neighbouring blocks of the previous pass.
+ * The plan image has the layout of a one-grid batch: size it with
+ * jacobi_pipelined_plan_bytes, copy it to the device, size the workspace
+ * with jacobi_batched_workspace and run it with jacobi_batched_run in
+ * JAC_BATCH_RELAXED mode (lockstep is refused, JAC_EARG).  a, b,
+ * out_idx_host and the errors are as for jacobi_batched_plan with n = 1. */
+typedef struct jac_pipeline {
+    int32_t dl, du, dt;
+} jac_pipeline_t;
 size_t jacobi_pipelined_plan_bytes(int dtype, const jac_grid_t *g, int T,
                                    const jac_tile_t *tile);
 int jacobi_pipelined_plan(int dtype, const jac_grid_t *g, void *a, void *b, int T,
-                          int team, const jac_tile_t *tile, void *plan_host,
+                          int team, const jac_pipeline_t *sync,
+                          const jac_tile_t *tile, void *plan_host,
                           size_t plan_bytes, int *out_idx_host);
 
 /* Compressed single grid: T sweeps in ONE array instead of two, the
- * "compressed grid" of Sect. 1.2 (results written to a location shifted
+ * "compressed grid" of Sect. 1.3 (results written to a location shifted
  * against the one they were read from, alternate passes shifting back), with
  * t sweeps fused per pass as in jacobi_tblock.
  *  Layout: with S = tile->t (1..JAC_MAX_DEPTH, required: the layout depends

@@ -21,6 +21,10 @@ Functions and the passages they follow:
   adjoint      -- gradient of a loss on level T with respect to level 0
                   (interior and shell) through the linear sweep operator.
   jacobi_solve -- all-FP64 Jacobi iteration to a relative residual tolerance.
+  lbm_d3q19    -- time steps of the D3Q19 lattice Boltzmann method (BGK,
+                  periodic box), the stencil method the paper takes the Jacobi
+                  sweep as a prototype of (Sect. 1.1); with lbm_lattice and
+                  lbm_equilibrium (lbm.c).
 """
 import ctypes
 import os
@@ -59,6 +63,14 @@ def _load():
                                         _L, ctypes.c_int, ctypes.POINTER(_L),
                                         ctypes.POINTER(ctypes.c_double)]
     lib.oracle_jacobi_solve.restype = ctypes.c_int
+    lib.oracle_lbm_lattice.argtypes = [np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"),
+                                       _dbl_p]
+    lib.oracle_lbm_lattice.restype = None
+    lib.oracle_lbm_equilibrium.argtypes = [ctypes.c_double] * 4 + [_dbl_p]
+    lib.oracle_lbm_equilibrium.restype = None
+    lib.oracle_lbm_d3q19.argtypes = [_L, _L, _L, _dbl_p, _dbl_p, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_int]
+    lib.oracle_lbm_d3q19.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -142,3 +154,31 @@ def jacobi_solve(x0, tol, check_every=50, max_sweeps=10**7, nthreads=0):
     if rc < 0:
         raise ValueError("oracle_jacobi_solve: bad arguments")
     return x, done.value, rel.value, rc == 0
+
+
+def lbm_lattice():
+    """(c, w): the D3Q19 velocities (19 x 3 ints) and weights (19 doubles)."""
+    c = np.zeros(57, dtype=np.int32)
+    w = np.zeros(19)
+    _load().oracle_lbm_lattice(c, w)
+    return c.reshape(19, 3), w
+
+
+def lbm_equilibrium(rho, ux, uy, uz):
+    """The 19 equilibrium populations of density rho and velocity (ux, uy, uz)."""
+    out = np.zeros(19)
+    _load().oracle_lbm_equilibrium(float(rho), float(ux), float(uy), float(uz), out)
+    return out
+
+
+def lbm_d3q19(f, omega, T, nthreads=0):
+    """Populations after T lattice Boltzmann steps (stream, then BGK collision
+    with rate omega) from ``f`` of shape (19, nz, ny, nx), periodic box."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.ndim != 4 or f.shape[0] != 19:
+        raise ValueError(f"populations must have shape (19, nz, ny, nx), got {f.shape}")
+    _, nz, ny, nx = f.shape
+    out = np.empty_like(f)
+    if _load().oracle_lbm_d3q19(nx, ny, nz, f, out, float(omega), int(T), nthreads) != 0:
+        raise ValueError("oracle_lbm_d3q19 failed")
+    return out

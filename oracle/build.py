@@ -9,7 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "oracle.c")
+SRC = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "lbm.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 CFLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
@@ -17,8 +17,9 @@ CFLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
 
 
 def build(verbose=False):
-    """Compile oracle.c into liboracle.so next to it; returns the library path."""
-    cmd = ["gcc", *CFLAGS, SRC, "-o", LIB + ".tmp", "-lm"]
+    """Compile oracle.c and lbm.c into liboracle.so next to them; returns the
+    library path."""
+    cmd = ["gcc", *CFLAGS, *SRC, "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

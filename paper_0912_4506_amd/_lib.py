@@ -15,6 +15,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "jacobi.h")
 JAC_F32, JAC_F64 = 0, 1
 JAC_OK, JAC_EARG, JAC_EHIP, JAC_EWORKSPACE, JAC_EUNSUPPORTED = 0, -1, -2, -3, -4
 MAX_DEPTH = 8
+ABI_VERSION = 2
 JAC_BATCH_RELAXED, JAC_BATCH_LOCKSTEP = 0, 1
 
 
@@ -26,6 +27,14 @@ class Grid(ctypes.Structure):
 class Tile(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int32), ("bx", ctypes.c_int32), ("by", ctypes.c_int32),
                 ("kchunk", ctypes.c_int32), ("waves", ctypes.c_int32)]
+
+
+class LbmGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
+
+
+class Pipeline(ctypes.Structure):
+    _fields_ = [("dl", ctypes.c_int32), ("du", ctypes.c_int32), ("dt", ctypes.c_int32)]
 
 
 class JacobiError(RuntimeError):
@@ -62,12 +71,15 @@ SIGNATURES = {
     "jacobi_batched_workspace": ([_P], ctypes.c_size_t),
     "jacobi_batched_run": ([_P, _P, _P, ctypes.c_size_t, ctypes.c_int, _P], ctypes.c_int),
     "jacobi_pipelined_plan_bytes": ([ctypes.c_int, _GP, ctypes.c_int, _TP], ctypes.c_size_t),
-    "jacobi_pipelined_plan": ([ctypes.c_int, _GP, _P, _P, ctypes.c_int, ctypes.c_int, _TP, _P,
-                               ctypes.c_size_t, _IP], ctypes.c_int),
+    "jacobi_pipelined_plan": ([ctypes.c_int, _GP, _P, _P, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(Pipeline), _TP, _P, ctypes.c_size_t, _IP],
+                              ctypes.c_int),
     "jacobi_compressed_workspace": ([ctypes.c_int, _GP, ctypes.c_int, _TP], ctypes.c_size_t),
     "jacobi_compressed": ([ctypes.c_int, _GP, _P, ctypes.c_int, _TP, _P, ctypes.c_size_t, _P, _IP],
                           ctypes.c_int),
     "jacobi_tile_menu": ([ctypes.c_int, _IP, ctypes.c_int], ctypes.c_int),
+    "lbm_d3q19_steps": ([ctypes.c_int, ctypes.POINTER(LbmGrid), _P, _P, ctypes.c_double,
+                         ctypes.c_int, _P, _IP], ctypes.c_int),
     "jacobi_autotune": ([ctypes.c_int, _GP, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _TP,
                          ctypes.POINTER(ctypes.c_float), _P], ctypes.c_int),
     "jacobi_default_tile": ([ctypes.c_int, _GP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _TP],
@@ -75,11 +87,16 @@ SIGNATURES = {
 }
 
 
+HEADERS = [HEADER, os.path.join(os.path.dirname(_HERE), "include", "lbm.h")]
+
+
 def declared_symbols():
-    """Function names include/jacobi.h declares."""
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(jacobi_\w+)\s*\(", text)))
+    """Function names the public headers (include/jacobi.h, include/lbm.h) declare."""
+    names = set()
+    for path in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:jacobi|lbm)_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def load():

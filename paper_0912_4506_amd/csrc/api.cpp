@@ -19,6 +19,7 @@
 
 #include "jacobi.h"
 #include "kernels.h"
+#include "lbm.h"
 
 namespace {
 
@@ -374,6 +375,34 @@ struct TraceSink {
     int64_t F = 0;
 };
 
+// Every pass of a temporally blocked run of T sweeps can run with this
+// blocking: the block has valid cells and fits the LDS at each pass depth
+// (the depths take at most two values).  Checked before anything is
+// enqueued, so a refused request leaves every buffer untouched.
+int check_tblock_plan(int dtype, const Geo &g, int T, const jac_tile_t &tile)
+{
+    const jac::TileShape *shape = find_shape(tile.bx, tile.by, tile.waves);
+    if (!shape)
+        return fail(JAC_EUNSUPPORTED, "no kernel for block shape %d x %d with %d waves", tile.bx,
+                    tile.by, tile.waves);
+    if (g.sz * (int64_t)elem_size(dtype) >= jac::kDropOffset)
+        return fail(JAC_EUNSUPPORTED, "planes of 2 GiB or more are not supported by the blocked kernels");
+    if (T <= 0)
+        return JAC_OK;
+    const int P = (T + tile.t - 1) / tile.t;
+    const int dlo = T / P, dhi = dlo + (T % P ? 1 : 0);
+    for (int depth : {dhi, dlo}) {
+        TbPlan plan;
+        if (!plan_ij(g, *shape, depth, &plan))
+            return fail(JAC_EUNSUPPORTED, "block %d x %d has no valid cells at depth %d", tile.bx,
+                        tile.by, depth);
+        if (shape_lds(dtype, *shape, depth) + 1024 > device_facts().lds_per_block)
+            return fail(JAC_EUNSUPPORTED, "block %d x %d at depth %d needs more LDS than the device has",
+                        tile.bx, tile.by, depth);
+    }
+    return JAC_OK;
+}
+
 // Enqueue the passes of a temporally blocked run (after copying a's shell
 // into b); *npasses receives the pass count.
 template <typename real>
@@ -384,8 +413,9 @@ int run_tblock(const Geo &g, real *a, real *b, int T, const jac_tile_t &tile, in
     const int dtype = sizeof(real) == 8 ? JAC_F64 : JAC_F32;
     const int P = (T + tile.t - 1) / tile.t;
     const DeviceFacts dev = device_facts();
-    if (g.sz * (int64_t)sizeof(real) >= jac::kDropOffset)
-        return fail(JAC_EUNSUPPORTED, "planes of 2 GiB or more are not supported by the blocked kernels");
+    int rc;
+    if ((rc = check_tblock_plan(dtype, g, T, tile)))
+        return rc;
     hipError_t e = jac::launch_copy_shell<real>(a, b, grid_args(g), st);
     if (e != hipSuccess)
         return hip_fail(e, "shell copy");
@@ -452,6 +482,10 @@ int run_adjoint(const Geo &g, real *la, real *lb, int T, const jac_tile_t &tile,
     real *G = (real *)ws, *S = G + F, *TR = S + F;
     const jac::GridArgs ga = grid_args(g);
     hipError_t e;
+    // refuse before the set-up below changes lam_a's shell faces
+    int rc0;
+    if ((rc0 = check_tblock_plan(sizeof(real) == 8 ? JAC_F64 : JAC_F32, g, T, tile)))
+        return rc0;
     if ((e = jac::launch_faces<real>(jac::FACES_SAVE, la, G, nullptr, nullptr, ga, F, 0, st)) ||
         (e = jac::launch_faces<real>(jac::FACES_ZERO, la, nullptr, nullptr, nullptr, ga, F, 0, st)) ||
         (e = jac::launch_faces<real>(jac::FACES_CLEAR_SUM, nullptr, nullptr, S, nullptr, ga, F, 0, st)))
@@ -1051,17 +1085,24 @@ size_t jacobi_batched_plan_bytes(int dtype, int n, const jac_grid_t *g, const in
 }
 
 // Plan image of a batched run.  team = 0: items pass by pass.  team >= 1
-// (one grid): the pipelined schedule of temporal blocking (Sect. 1.2, 1.3)
+// (one grid): the pipelined schedule of temporal blocking (Sect. 1.3)
 // in GPU form.  The passes form segments of `team` consecutive passes; within
-// a segment, wavefront w holds pass seg + s on k chunk w - s for every s, so
-// pass p works on the chunk just behind the one pass p-1 works on, like the
-// threads of a team following each other through the blocks of a shared
-// cache.  Every item's neighbours of the previous pass come earlier in this
-// order (same or earlier wavefront, earlier pass), which keeps the relaxed
-// waits deadlock-free.
+// a segment, wavefront w holds pass seg + s on k chunk w - s * (dl + 1), so
+// pass p works dl + 1 chunks behind pass p-1 (one chunk of halo plus the
+// lower distance), like the threads of a team following each other through
+// the blocks of a shared cache.  Every counter an item waits on belongs to an
+// earlier item in this order, which keeps the relaxed waits deadlock-free:
+//  * the 27 neighbours of the previous pass (chunks tk-1..tk+1) and the
+//    previous pass's chunk tk + dl: the same or an earlier wavefront,
+//    earlier pass;
+//  * the team delay: a segment's front pass waits on the previous
+//    segment, all of which comes earlier;
+//  * the upper bound, the next pass's chunk tk - du - 2: wavefront
+//    w + dl - du - 1, earlier because du >= dl (checked); a segment's rear
+//    pass does not wait on the next segment (which comes later).
 static int build_plan(int dtype, int n, const jac_grid_t *g, void *const *a, void *const *b,
                       const int *T, const jac_tile_t *tile, void *plan_host, size_t plan_bytes,
-                      int *out_idx_host, int team)
+                      int *out_idx_host, int team, const jac_pipeline_t &sync)
 {
     jac_tile_t tl;
     GridPlan *plans = nullptr;
@@ -1131,6 +1172,10 @@ static int build_plan(int dtype, int n, const jac_grid_t *g, void *const *a, voi
         G.passes = gp.passes;
         G.tiles = gp.tiles;
         G.counter_off = off;
+        G.team = team;
+        G.dl = team > 0 ? sync.dl : 1;
+        G.du = team > 0 ? sync.du : 0;
+        G.dt = team > 0 ? sync.dt : 0;
         off += gp.tiles;
         out_idx_host[m] = gp.passes % 2;
         const int64_t sh = (gp.geo.nx + 2) * (gp.geo.ny + 2) + (gp.geo.nx + 2) * (gp.geo.nz + 2) +
@@ -1151,15 +1196,16 @@ static int build_plan(int dtype, int n, const jac_grid_t *g, void *const *a, voi
     } else {
         const GridPlan &gp = plans[0];
         const int P = gp.passes, nq = gp.tp.nkc, nij = gp.tp.nti * gp.tp.ntj;
+        const int lag = sync.dl + 1;
         for (int seg = 0; seg < P; seg += team) {
             const int pe = std::min(P, seg + team);
-            for (int w = 0; w < nq + (pe - seg) - 1; ++w)
+            for (int64_t w = 0; w < nq + (int64_t)(pe - seg - 1) * lag; ++w)
                 for (int pass = seg; pass < pe; ++pass) {
-                    const int q = w - (pass - seg);
+                    const int64_t q = w - (int64_t)(pass - seg) * lag;
                     if (q < 0 || q >= nq)
                         continue;
                     for (int ij = 0; ij < nij; ++ij)
-                        items[it++] = jac::BatchItem{0, pass, q * nij + ij, 0};
+                        items[it++] = jac::BatchItem{0, pass, (int)q * nij + ij, 0};
                 }
         }
         // pass ranges do not exist in this order (lockstep runs are refused)
@@ -1176,7 +1222,8 @@ int jacobi_batched_plan(int dtype, int n, const jac_grid_t *g, void *const *a, v
                         int *out_idx_host)
 {
     g_err.clear();
-    return build_plan(dtype, n, g, a, b, T, tile, plan_host, plan_bytes, out_idx_host, 0);
+    return build_plan(dtype, n, g, a, b, T, tile, plan_host, plan_bytes, out_idx_host, 0,
+                      jac_pipeline_t{1, 0, 0});
 }
 
 size_t jacobi_pipelined_plan_bytes(int dtype, const jac_grid_t *g, int T, const jac_tile_t *tile)
@@ -1189,17 +1236,25 @@ size_t jacobi_pipelined_plan_bytes(int dtype, const jac_grid_t *g, int T, const 
 }
 
 int jacobi_pipelined_plan(int dtype, const jac_grid_t *g, void *a, void *b, int T, int team,
-                          const jac_tile_t *tile, void *plan_host, size_t plan_bytes,
-                          int *out_idx_host)
+                          const jac_pipeline_t *sync, const jac_tile_t *tile, void *plan_host,
+                          size_t plan_bytes, int *out_idx_host)
 {
     g_err.clear();
     if (team < 1 || team > 1024)
         return fail(JAC_EARG, "team = %d outside 1..1024", team);
+    const jac_pipeline_t sy = sync ? *sync : jac_pipeline_t{1, 0, 0};
+    if (sy.dl < 1 || sy.dl > 4096)
+        return fail(JAC_EARG, "lower distance dl = %d outside 1..4096", sy.dl);
+    if (sy.du != 0 && (sy.du < sy.dl || sy.du > 4096))
+        return fail(JAC_EARG, "upper distance du = %d must be 0 (none) or in dl..4096 (dl = %d)", sy.du,
+                    sy.dl);
+    if (sy.dt < 0 || sy.dt > 4096)
+        return fail(JAC_EARG, "team delay dt = %d outside 0..4096", sy.dt);
     jac_tile_t req = tile ? *tile : jac_tile_t{0, 0, 0, 0, 0};
     if (req.kchunk == 0)
         req.kchunk = PIPELINE_KCHUNK;
     void *aa[1] = {a}, *bb[1] = {b};
-    return build_plan(dtype, 1, g, aa, bb, &T, &req, plan_host, plan_bytes, out_idx_host, team);
+    return build_plan(dtype, 1, g, aa, bb, &T, &req, plan_host, plan_bytes, out_idx_host, team, sy);
 }
 
 static int read_header(const void *plan_host, jac::BatchHeader *h)
@@ -1384,6 +1439,52 @@ int jacobi_copy(void *dst, const void *src, size_t bytes, void *stream)
         return JAC_OK;
     hipError_t e = jac::launch_copy(dst, src, bytes, (hipStream_t)stream);
     return e == hipSuccess ? JAC_OK : hip_fail(e, "copy launch");
+}
+
+int lbm_d3q19_steps(int dtype, const lbm_grid_t *g, void *f, void *f_tmp, double omega, int T,
+                    void *stream, int *out_idx)
+{
+    g_err.clear();
+    int rc;
+    if ((rc = check_dtype(dtype)))
+        return rc;
+    if (!g)
+        return fail(JAC_EARG, "grid descriptor is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(JAC_EARG, "box extents must be >= 1, got %lld x %lld x %lld", (long long)g->nx,
+                    (long long)g->ny, (long long)g->nz);
+    if (g->nx > (1 << 30) || g->ny > (1 << 30) || g->nz > 65535)
+        return fail(JAC_EARG, "box too large (nx, ny <= 2^30, nz <= 65535)");
+    const long double cells = (long double)g->nx * g->ny * g->nz;
+    if (cells * 19 > (long double)(INT64_MAX / 16) ||
+        (long double)((g->nx + 63) / 64) * ((g->ny + 3) / 4) * g->nz > (long double)INT_MAX / 2)
+        return fail(JAC_EARG, "box too large");
+    if ((rc = check_ptr(f, dtype, "f")) || (rc = check_ptr(f_tmp, dtype, "f_tmp")))
+        return rc;
+    const int64_t n = g->nx * g->ny * g->nz;
+    const size_t bytes = (size_t)(19 * n) * elem_size(dtype);
+    if (overlap(f, bytes, f_tmp, bytes))
+        return fail(JAC_EARG, "f and f_tmp overlap");
+    if (!(omega == omega) || omega > 1e300 || omega < -1e300)
+        return fail(JAC_EARG, "omega must be finite");
+    if (T < 0)
+        return fail(JAC_EARG, "T = %d is negative", T);
+    if (!out_idx)
+        return fail(JAC_EARG, "out_idx is NULL");
+    *out_idx = 0;
+    jac::LbmArgs p{(int)g->nx, (int)g->ny, (int)g->nz, n, omega};
+    hipStream_t st = (hipStream_t)stream;
+    for (int s = 0; s < T; ++s) {
+        void *src = (s % 2 == 0) ? f : f_tmp;
+        void *dst = (s % 2 == 0) ? f_tmp : f;
+        hipError_t e = dtype == JAC_F64
+                           ? jac::launch_lbm_d3q19<double>((const double *)src, (double *)dst, p, st)
+                           : jac::launch_lbm_d3q19<float>((const float *)src, (float *)dst, p, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "lattice Boltzmann launch");
+    }
+    *out_idx = T % 2;
+    return JAC_OK;
 }
 
 int jacobi_tile_menu(int dtype, int *shapes_host, int cap)

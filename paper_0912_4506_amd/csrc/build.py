@@ -21,7 +21,7 @@ ARCH = "gfx950"
 SOURCES = ["tb_plain_f64.hip", "tb_plain_f32.hip", "tb_rhs_f64.hip", "tb_rhs_f32.hip",
            "tb_trace_f64.hip", "tb_trace_f32.hip", "tb_batch_f64.hip", "tb_batch_f32.hip",
            "tb_comp_f64.hip", "tb_comp_f32.hip",
-           "kernels.hip", "api.cpp"]
+           "kernels.hip", "lbm.hip", "api.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -6,24 +6,73 @@
 namespace jac {
 
 // ---------------------------------------------------------------- division --
-// Correctly rounded s/6 in three operations (Markstein's correction step):
-// q0 = s * fl(1/6) is within one ulp of s/6, the residual s - 6 q0 is exact in
-// an FMA, and q0 + r * fl(1/6) rounds to the correctly rounded quotient
-// (P. Markstein, IBM J. Res. Dev. 34(1), 1990; Muller et al., Handbook of
-// Floating-Point Arithmetic, division by a correctly rounded reciprocal).
-// Valid away from overflow and underflow, i.e. for |s| in [2^-1020, 2^1020]
-// and s = 0; the tests compare it bitwise with IEEE division.
+// s/6 in three operations (Markstein's correction step): q0 = s * fl(1/6) is
+// within one ulp of s/6, the residual 6 q0 - s is exact in an FMA, and
+// q0 - r * fl(1/6) rounds to the correctly rounded quotient (P. Markstein,
+// IBM J. Res. Dev. 34(1), 1990; Muller et al., Handbook of Floating-Point
+// Arithmetic, division by a correctly rounded reciprocal).  Taking the
+// residual with the opposite sign keeps the sign of a zero quotient: for
+// s = -0 the last FMA adds -0 to -0.
+//
+// Where the three operations can differ from IEEE s/6:
+//  * s = +-Inf: 6 q0 - s is Inf - Inf, so the result is NaN (IEEE: +-Inf);
+//  * a quotient in the subnormal range: there s/6 can fall exactly half way
+//    between two subnormals (s = 9 * 2^-1074 gives 1.5 * 2^-1074), and
+//    q0 - r * fl(1/6), a hair below that, rounds the other way.
+// A quotient that comes out as a normal number or zero is the IEEE one: in
+// the normal range s/6 is never a tie (a tie would make s an odd multiple of
+// three half-ulps of the quotient, which needs more than 53 bits), and the
+// FMA's error is far below the distance to the nearest midpoint.  So
+// div6_suspect flags exactly the results worth recomputing (NaN, Inf,
+// subnormal) and callers redo those with div6_ieee; for finite data away from
+// the subnormal range the check never fires.
 __device__ __forceinline__ double div6(double s)
 {
     const double c = 0x1.5555555555555p-3;  // the double nearest 1/6
     const double q = s * c;
-    const double r = __fma_rn(-6.0, q, s);
-    return __fma_rn(r, c, q);
+    const double r = __fma_rn(6.0, q, -s);
+    return __fma_rn(-r, c, q);
 }
 
 __device__ __forceinline__ float div6(float s)
 {
     return s * (1.0f / 6.0f);
+}
+
+// v_cmp_class mask: signalling and quiet NaN, -Inf, -subnormal, +subnormal,
+// +Inf (the zero and normal classes are exact results of div6)
+constexpr int kDiv6SuspectClass = 0x001 | 0x002 | 0x004 | 0x010 | 0x080 | 0x200;
+
+__device__ __forceinline__ bool div6_suspect(double q)
+{
+    return __builtin_amdgcn_class(q, kDiv6SuspectClass);
+}
+
+// FP32 sweeps multiply by the float nearest 1/6; nothing to recompute
+__device__ __forceinline__ bool div6_suspect(float) { return false; }
+
+// IEEE division (the compiler's correctly rounded sequence, valid for every
+// input, including subnormals and infinities)
+__device__ __forceinline__ double div6_ieee(double s) { return s / 6.0; }
+__device__ __forceinline__ float div6_ieee(float s) { return s * (1.0f / 6.0f); }
+
+// s/6 with the IEEE result everywhere: the fast quotient, recomputed where it
+// may differ (one class test per value; used outside the blocked pass)
+template <typename real>
+__device__ __forceinline__ real div6_exact(real s)
+{
+    const real q = div6(s);
+    return div6_suspect(q) ? div6_ieee(s) : q;
+}
+
+// An opaque copy of v: the compiler cannot prove it equal to v, so an
+// expression recomputed from it is not merged with the original (which
+// would keep the original result live in registers until the recompute).
+template <typename real>
+__device__ __forceinline__ real opaque(real v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
 // s_waitcnt immediate (gfx9 encoding) that waits until at most n vector

@@ -110,6 +110,10 @@ struct BatchGrid {
     int nx, ny, nz;
     int nti, ntj, nkc, hi, kchunk;
     int T, passes, tiles, counter_off;
+    // pipelined runs (relaxed synchronisation, Eq. 3): passes per segment
+    // (0: not pipelined), lower and upper distances and team delay in k
+    // chunks beyond the one-chunk halo (du = 0: no upper bound)
+    int team, dl, du, dt;
 };
 
 // One block of one pass of one grid.  Items are ordered pass by pass, or in
@@ -183,6 +187,17 @@ hipError_t launch_batched(int dtype, int cfg, int depth, int fixed, const BatchL
                           hipStream_t st);
 int batched_occupancy(int dtype, int cfg, int depth, int fixed);
 int batched_scratch(int dtype, int cfg, int depth, int fixed);
+
+// D3Q19 lattice Boltzmann step (lbm.hip): populations of a periodic nx x ny x
+// nz box, 19 arrays of n = nx*ny*nz values, streamed and collided from f
+// into out.
+struct LbmArgs {
+    int nx, ny, nz;
+    int64_t n;
+    double omega;
+};
+template <typename real>
+hipError_t launch_lbm_d3q19(const real *f, real *out, const LbmArgs &p, hipStream_t st);
 
 // Per-lane scratch (register spill) bytes of a tblock instance, -1 if none.
 int tblock_scratch(int dtype, int cfg, int depth, int mode);

@@ -83,6 +83,8 @@ __global__ __launch_bounds__(NT) void plain_kernel(const real *__restrict__ A,
         // the same 2 x RB stores every step (cells outside the grid get the
         // drop offset), so the wait for the next plane skips the stores
         const auto rs = plane_rsrc(B + (int64_t)k * p.sz, (int)(p.sz * (int64_t)sizeof(real)));
+        real sum[RB][2], q[RB][2];
+        bool odd = false;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             real s0 = cw[r] + cur[r + 1][1];
@@ -95,14 +97,33 @@ __global__ __launch_bounds__(NT) void plain_kernel(const real *__restrict__ A,
             s1 = s1 + cur[r + 2][1];
             s1 = s1 + prev[r][1];
             s1 = s1 + nxt[r + 1][1];
+            sum[r][0] = s0;
+            sum[r][1] = s1;
+            q[r][0] = div6(s0);
+            q[r][1] = div6(s1);
+            odd = odd || div6_suspect(q[r][0]) || div6_suspect(q[r][1]);
+        }
+        // quotients the three-operation division may get wrong (NaN, Inf,
+        // subnormal) are redone with IEEE division: one wave-uniform test per
+        // step, so the plain sweep is IEEE-exact for every input
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(odd) != 0, 0)) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    if (div6_suspect(q[r][c]))
+                        q[r][c] = div6_ieee(sum[r][c]);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
             const bool row = j0 + r <= p.ny;
             const int o0 = row && i0 <= p.nx ? (int)((ro[r + 1] + i0) * (int64_t)sizeof(real))
                                              : kDropOffset;
             const int o1 = row && i0 + 1 <= p.nx
                                ? (int)((ro[r + 1] + i0 + 1) * (int64_t)sizeof(real))
                                : kDropOffset;
-            plane_store(div6(s0), rs, o0);
-            plane_store(div6(s1), rs, o1);
+            plane_store(q[r][0], rs, o0);
+            plane_store(q[r][1], rs, o1);
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
@@ -401,7 +422,7 @@ __global__ void face_finalize_kernel(real *__restrict__ grid, const real *__rest
 {
     for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < F;
          f += (int64_t)gridDim.x * blockDim.x)
-        grid[face_offset(f, g)] = G[f] + div6(S[f]);
+        grid[face_offset(f, g)] = G[f] + div6_exact(S[f]);
 }
 
 // The whole shell of a grid (six faces with their edges and corners) as one

@@ -553,7 +553,7 @@ __global__ __launch_bounds__(64 * W) void tblock_kernel(TbArgs<real> p)
     tb_tile<real, TL, CI, R, W, MODE>(p, ti, tj, k0, min(k0 + p.kchunk, p.nz + 1), TL, xch);
 }
 
-// One pass of the compressed single grid (Sect. 1.2): src and dst are two
+// One pass of the compressed single grid (Sect. 1.3): src and dst are two
 // frames of one array, dst shifted by (-shift, -shift, 0) cells against src
 // (dir = +1) or by (+shift, +shift, 0) (dir = -1), shift >= the halo.  A
 // block then overwrites only inputs of itself and of its neighbours at -1
@@ -630,22 +630,42 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
         const int tj = (m.tile / G.nti) % G.ntj;
         const int tk = m.tile / (G.nti * G.ntj);
         int *cnt = L.counters + 1 + G.counter_off;
-        if (L.persistent && m.pass > 0) {
-            // wave 0 polls the 27 neighbour counters at once, lane n the block
-            // at offset (n % 3, n / 3 % 3, n / 9) - 1, until every lane sees
-            // its condition hold
+        if (L.persistent && (m.pass > 0 || G.team > 0)) {
+            // wave 0 polls every counter the item waits on at once, until
+            // every lane sees its condition hold:
+            //  * lanes 0..26: the block at offset (n % 3, n / 3 % 3, n / 9) - 1
+            //    has finished the previous pass (the data the item reads);
+            //  * pipelined runs (Eq. 3, distances in k chunks beyond the
+            //    one-chunk halo): lane 27, the previous pass has finished the
+            //    same block column's chunk tk + dl (+ dt at a segment's front,
+            //    the team delay); lane 28, the next pass has finished chunk
+            //    tk - du - 2 (the upper bound; not at a segment's rear pass)
             if (threadIdx.x < 64) {
                 const int n = threadIdx.x;
-                const int a = ti + n % 3 - 1, b = tj + n / 3 % 3 - 1, c = tk + n / 9 - 1;
-                const bool mine = n < 27 && a >= 0 && a < G.nti && b >= 0 && b < G.ntj && c >= 0 &&
-                                  c < G.nkc;
+                int a = ti, b = tj, c = tk, need = m.pass;
+                bool mine = false;
+                if (n < 27) {
+                    a = ti + n % 3 - 1;
+                    b = tj + n / 3 % 3 - 1;
+                    c = tk + n / 9 - 1;
+                    mine = m.pass > 0;
+                } else if (n == 27 && G.team > 0 && m.pass > 0) {
+                    c = min(tk + G.dl + (m.pass % G.team == 0 ? G.dt : 0), G.nkc - 1);
+                    mine = true;
+                } else if (n == 28 && G.team > 0 && G.du > 0 && m.pass % G.team != G.team - 1 &&
+                           m.pass + 1 < G.passes) {
+                    c = tk - G.du - 2;
+                    need = m.pass + 2;
+                    mine = c >= 0;
+                }
+                mine = mine && a >= 0 && a < G.nti && b >= 0 && b < G.ntj && c >= 0 && c < G.nkc;
                 const int *q = cnt + (mine ? (c * G.ntj + b) * G.nti + a : 0);
                 // bounded wait (seconds): a wait that cannot end raises the
                 // error flag instead of hanging; every decision is wave-uniform
                 int spins = 0;
                 for (;;) {
                     const bool ok =
-                        !mine || __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= m.pass;
+                        !mine || __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
                     if (__all(ok))
                         break;
                     __builtin_amdgcn_s_sleep(2);

@@ -16,6 +16,11 @@ set; every workload here is synthetic):
   * batch_edges: 64 cubic interior edges, e = clip(round(exp(U(ln 32, ln 256))),
     32, 256) from ``default_rng(seed)``; ``cubic=False`` draws the three axes
     independently.  Grid g of a batch is ``grid(..., seed=[seed, g])``.
+  * lbm_populations(nx, ny, nz, seed): 19 arrays of (nz, ny, nx) values
+    (1 + 0.1 U[0, 1)) / 19 from ``default_rng(seed)``: positive populations
+    with density near 1 and a small random velocity, far from equilibrium
+    (the lattice Boltzmann workload; its time per step does not depend on the
+    values).
 """
 import math
 
@@ -61,3 +66,10 @@ def batch_grid(shape, index, seed=0, dtype=np.float64):
     """Grid ``index`` of a batch: uniform [0, 1) from ``default_rng([seed, index])``."""
     nx, ny, nz = shape
     return grid(nx, ny, nz, seed=[seed, index], dtype=dtype)
+
+
+def lbm_populations(nx, ny, nz, seed=0, dtype=np.float64):
+    """(19, nz, ny, nx) positive populations, (1 + 0.1 U[0, 1)) / 19."""
+    rng = np.random.default_rng(seed)
+    f = (1.0 + 0.1 * rng.random((19, nz, ny, nx))) / 19.0
+    return f.astype(dtype, copy=False)

@@ -226,10 +226,11 @@ class BatchPlan:
         B = (ctypes.c_void_p * n)(*[x.data_ptr() for x in grids_b])
         tile = _tile(t, bx, by, kchunk, waves)
         nbytes = lib.jacobi_batched_plan_bytes(code, n, G, T, ctypes.byref(tile))
-        if nbytes == 0:
-            check(_lib.JAC_EARG)
-        self._host = (ctypes.c_ubyte * nbytes)()
         self.out_idx = (ctypes.c_int * n)()
+        if nbytes == 0:     # the plan call repeats the failed check and returns its code
+            check(lib.jacobi_batched_plan(code, n, G, A, B, T, ctypes.byref(tile), None, 0,
+                                          self.out_idx) or _lib.JAC_EARG)
+        self._host = (ctypes.c_ubyte * nbytes)()
         check(lib.jacobi_batched_plan(code, n, G, A, B, T, ctypes.byref(tile), self._host, nbytes,
                                       self.out_idx))
         dev = grids_a[0].device
@@ -256,10 +257,13 @@ class BatchPlan:
 class PipelinePlan(BatchPlan):
     """Pipelined temporal blocking of one grid (jacobi_pipelined_plan): T
     sweeps as passes of t sweeps per block, segments of `team` passes
-    streaming through k chunks of `kchunk` planes one chunk apart.  Runs in
-    relaxed mode only; results()[0] holds level T."""
+    streaming through k chunks of `kchunk` planes a few chunks apart, with
+    the relaxed synchronisation of Eq. 3: lower distance dl, upper distance
+    du (0: none; dl = du = 1 is lock-step) and team delay dt, in chunks
+    beyond the one-chunk halo.  Runs in relaxed mode only; results()[0]
+    holds level T."""
 
-    def __init__(self, a, b, T, team=4, t=1, bx=0, by=0, kchunk=0, waves=0):
+    def __init__(self, a, b, T, team=4, t=1, bx=0, by=0, kchunk=0, waves=0, dl=1, du=0, dt=0):
         _same(a, b)
         self.a, self.b = [a], [b]
         self.dtype = a.dtype
@@ -267,23 +271,27 @@ class PipelinePlan(BatchPlan):
         code = dtype_code(a)
         g = grid_of(a)
         tile = _tile(t, bx, by, kchunk, waves)
+        sync = _lib.Pipeline(int(dl), int(du), int(dt))
         nbytes = lib.jacobi_pipelined_plan_bytes(code, ctypes.byref(g), int(T), ctypes.byref(tile))
-        if nbytes == 0:
-            check(_lib.JAC_EARG)
-        self._host = (ctypes.c_ubyte * nbytes)()
         self.out_idx = (ctypes.c_int * 1)()
+        if nbytes == 0:     # the plan call repeats the failed check and returns its code
+            check(lib.jacobi_pipelined_plan(code, ctypes.byref(g), _ptr(a), _ptr(b), int(T),
+                                            int(team), ctypes.byref(sync), ctypes.byref(tile), None,
+                                            0, self.out_idx) or _lib.JAC_EARG)
+        self._host = (ctypes.c_ubyte * nbytes)()
         check(lib.jacobi_pipelined_plan(code, ctypes.byref(g), _ptr(a), _ptr(b), int(T), int(team),
-                                        ctypes.byref(tile), self._host, nbytes, self.out_idx))
+                                        ctypes.byref(sync), ctypes.byref(tile), self._host, nbytes,
+                                        self.out_idx))
         self.plan_dev = torch.frombuffer(bytearray(self._host), dtype=torch.uint8).to(a.device)
         ws = lib.jacobi_batched_workspace(self._host)
         self.ws = torch.zeros(max(ws, 8), dtype=torch.uint8, device=a.device)
         self.device = a.device
 
 
-def pipelined(a, b, T, team=4, t=1, bx=0, by=0, kchunk=0, waves=0):
+def pipelined(a, b, T, team=4, t=1, bx=0, by=0, kchunk=0, waves=0, dl=1, du=0, dt=0):
     """Level T of grid a by pipelined temporal blocking; returns the tensor
     (a or b) that holds it."""
-    return PipelinePlan(a, b, T, team, t, bx, by, kchunk, waves).run("relaxed").results()[0]
+    return PipelinePlan(a, b, T, team, t, bx, by, kchunk, waves, dl, du, dt).run("relaxed").results()[0]
 
 
 def compressed_shape(nx, ny, nz, t):
@@ -400,3 +408,20 @@ def autotune_batch(grids_a, grids_b, Ts, candidates=None, mode="relaxed", reps=2
         if ms < best_ms:
             best, best_ms = (t, bx, by, w), ms
     return best, best_ms
+
+
+def lbm_d3q19(f, f_tmp, omega, T):
+    """T D3Q19 lattice Boltzmann steps (BGK, periodic box) on populations f of
+    shape (19, nz, ny, nx) (contiguous, float32 or float64); f_tmp is a second
+    buffer like f.  Returns the tensor (f or f_tmp) holding step T."""
+    if f.shape != f_tmp.shape or f.dtype != f_tmp.dtype or f.device != f_tmp.device:
+        raise ValueError("f and f_tmp must share shape, dtype and device")
+    if f.dim() != 4 or f.shape[0] != 19 or not (f.is_contiguous() and f_tmp.is_contiguous()):
+        raise ValueError("populations must be contiguous tensors of shape (19, nz, ny, nx)")
+    _, nz, ny, nx = f.shape
+    out = ctypes.c_int(0)
+    with torch.cuda.device(f.device):
+        check(_lib.load().lbm_d3q19_steps(dtype_code(f), ctypes.byref(_lib.LbmGrid(nx, ny, nz)),
+                                          _ptr(f), _ptr(f_tmp), float(omega), int(T), _stream(f),
+                                          ctypes.byref(out)))
+    return f_tmp if out.value else f

@@ -20,7 +20,7 @@ def test_exports_every_declared_symbol(lib):
     missing = [s for s in declared if not hasattr(lib, s)]
     assert not missing, missing
     assert set(declared) == set(_lib.SIGNATURES), "binding and header disagree"
-    assert lib.jacobi_version() == 1
+    assert lib.jacobi_version() == 2
 
 
 P = ctypes.c_void_p
@@ -169,3 +169,24 @@ def test_compressed_checks(lib):
     assert call(ws=P((1 << 20) + 256)) == JAC_EARG and "overlaps" in err(lib)
     assert call(outp=False) == JAC_EARG and "out_frame" in err(lib)
     assert call(T=0) == 0 and out.value == 0          # nothing enqueued
+
+
+def test_lbm_argument_checks(lib):
+    from paper_0912_4506_amd._lib import LbmGrid
+    g = LbmGrid(8, 8, 8)
+    n = 19 * 8 * 8 * 8 * 8
+
+    def call(grid=g, f=A, ft=P((1 << 20) + n), omega=1.0, T=2, dtype=1):
+        return lib.lbm_d3q19_steps(dtype, ctypes.byref(grid) if grid is not None else None, f, ft,
+                                   omega, T, None, ctypes.byref(OUT))
+
+    assert call(grid=None) == JAC_EARG and "NULL" in err(lib)
+    assert call(grid=LbmGrid(0, 8, 8)) == JAC_EARG and "extents" in err(lib)
+    assert call(grid=LbmGrid(8, 8, 70000)) == JAC_EARG and "large" in err(lib)
+    assert call(ft=P((1 << 20) + n - 8)) == JAC_EARG and "overlap" in err(lib)
+    assert call(f=None) == JAC_EARG
+    assert call(omega=float("nan")) == JAC_EARG and "omega" in err(lib)
+    assert call(T=-1) == JAC_EARG
+    assert call(dtype=3) == JAC_EARG
+    OUT.value = 5
+    assert call(T=0) == 0 and OUT.value == 0

@@ -125,3 +125,15 @@ def test_config_256_t32_fp64_bitwise(jac):
     ref = oracle.adjoint(lam, T)
     got = gpu_adjoint(jac, lam, T, t=8)
     assert np.array_equal(got, ref)
+
+
+def test_config_256_t32_fp32(jac):
+    """The differentiable workload in FP32: 256^3, T = 32, t = 8, against the
+    oracle's FP64 adjoint of the FP32-rounded gradient.  The interior values
+    are averages (bounded by the input's max); the shell gradient adds up to
+    T of them, divided by 6."""
+    n, T = 256, 32
+    lam = (2 * inputs.adjoint_weights(n, n, n, seed=0) * inputs.grid(n, n, n, seed=0)).astype(np.float32)
+    ref = oracle.adjoint(lam.astype(np.float64), T)
+    got = gpu_adjoint(jac, lam, T, dtype=torch.float32, t=8)
+    assert np.max(np.abs(got - ref)) <= 1e-5 * max(1.0, T / 6.0)

@@ -145,3 +145,76 @@ def test_batched_random_configs(jac, case):
                 assert np.array_equal(got, ref), (case, rep, m, shapes[m], Ts[m], t, bx, by, w, kc)
             else:
                 assert np.max(np.abs(got - ref)) <= 1e-5, (case, rep, m)
+
+
+@pytest.fixture(scope="module")
+def batch64():
+    """The batched workload (64 cubic grids, edges log-uniform in [32, 256],
+    FP64, T = 50): level-0 grids on the host, the oracle's results on the GPU."""
+    edges = inputs.batch_edges(64, seed=0)
+    us = [inputs.batch_grid(e, m, seed=0) for m, e in enumerate(edges)]
+    refs = [torch.from_numpy(oracle.sweeps(u, 50)).to("cuda") for u in us]
+    yield us, refs
+    del refs
+    torch.cuda.empty_cache()
+
+
+def test_batch_64_grids_every_autotune_candidate(jac, batch64):
+    """Every (t, block) the batch autotuner can pick for the benchmark's
+    workload (depths 2..6 times the menu; the benchmark times the pick, in a
+    graph replay): one persistent launch each, every grid bitwise."""
+    from paper_0912_4506_amd._lib import JacobiError, JAC_EUNSUPPORTED
+    us, refs = batch64
+    a = [torch.from_numpy(u).to("cuda") for u in us]
+    a0 = [x.clone() for x in a]
+    b = [torch.empty_like(x) for x in a]
+    ran = 0
+    for (bx, by, w) in jac.tile_menu(torch.float64):
+        for t in range(2, 7):
+            try:
+                plan = jac.BatchPlan(a, b, [50] * 64, t=t, bx=bx, by=by, waves=w)
+            except JacobiError as e:
+                assert e.code == JAC_EUNSUPPORTED, e
+                continue
+            for x, x0 in zip(a, a0):
+                x.copy_(x0)
+            for x in b:
+                x.fill_(float("nan"))
+            plan.run("relaxed")
+            torch.cuda.synchronize()
+            assert not plan.wait_error(), (t, bx, by, w)
+            for m, (ref, out) in enumerate(zip(refs, plan.results())):
+                assert torch.equal(out, ref), (t, bx, by, w, m)
+            ran += 1
+    assert ran >= 20
+
+
+def test_batch_64_grids_graph_replays_bench_pick(jac, batch64):
+    """The benchmark's launch: depth 5, 64 x 64 blocks of 16 waves (the
+    constant-depth instance, every T a multiple of t), captured in a graph
+    and replayed three times; every replay of every grid bitwise."""
+    us, refs = batch64
+    a = [torch.from_numpy(u).to("cuda") for u in us]
+    a0 = [x.clone() for x in a]
+    b = [torch.empty_like(x) for x in a]
+    plan = jac.BatchPlan(a, b, [50] * 64, t=5, bx=64, by=64, waves=16)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run("relaxed")
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.run("relaxed")
+    for rep in range(3):
+        for x, x0 in zip(a, a0):
+            x.copy_(x0)
+        for x in b:
+            x.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert not plan.wait_error()
+        for m, (ref, out) in enumerate(zip(refs, plan.results())):
+            assert torch.equal(out, ref), (rep, m)

@@ -178,3 +178,27 @@ def test_autotune_choice_is_used_and_exact(jac):
     a = dev(u)
     out = jac.tblock(a, torch.empty_like(a), T)
     assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T))
+
+
+def test_refused_tile_leaves_buffers_untouched(jac):
+    """A block the library refuses at the requested depth is refused before
+    anything is enqueued: a, b (and the adjoint's lam_a) keep their contents."""
+    from paper_0912_4506_amd._lib import JacobiError, JAC_EUNSUPPORTED
+    u = inputs.grid(40, 30, 20, seed=4)
+    bad = [(bx, by, w) for bx, by, w in jac.tile_menu(torch.float64) if not fits(bx, by, 8)]
+    assert bad
+    for bx, by, w in bad:
+        a = dev(u)
+        b = torch.full_like(a, float("nan"))
+        with pytest.raises(JacobiError) as e:
+            jac.tblock(a, b, 16, t=8, bx=bx, by=by, waves=w)
+        assert e.value.code == JAC_EUNSUPPORTED
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy(), u)
+        assert bool(torch.isnan(b).all())
+        with pytest.raises(JacobiError) as e:
+            jac.adjoint(a, b, 16, t=8, bx=bx, by=by, waves=w)
+        assert e.value.code == JAC_EUNSUPPORTED
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy(), u)
+        assert bool(torch.isnan(b).all())

@@ -1,20 +1,20 @@
 """GPU parity at the full workload sizes, in the launch configurations the
-benchmark times.
+benchmark times, compared over the whole grid.
 
-* 512^3 FP64, T = 100: the plain kernel and the blocked pass at every depth
-  the benchmark reports (the library's default block for each), compared
-  bitwise with the oracle at sampled cells, which the oracle computes one by
-  one from their domain of dependence.  The samples include the shell
-  corners, the edges of the blocks and k chunks the default plan uses, and
-  random interior cells.
-* The same 512^3 grid by the pipelined schedule and in one array (the
-  compressed grid), bitwise, and in FP32 at the default blocking (within 1e-5
-  of the oracle on the FP32-rounded input).
+* 512^3 FP64, T = 100: the plain kernel, and the blocked pass at every depth
+  the benchmark reports with the library's default block, and at depths 4
+  and 5 (the headline depth and its neighbour) with every block shape of the
+  menu (the by-depth figures time each shape): bitwise, every cell, against
+  the oracle's full run (about 2 s on the host).  The comparison runs on the
+  GPU against an uploaded copy of the oracle's result.
+* The same grid by the pipelined schedule and in one array (the compressed
+  grid) at the configurations the benchmark reports, bitwise; and in FP32 at
+  the default blocking, every cell within 1e-5 of the FP64 oracle run on the
+  FP32-rounded input.
 * 768^3, the refinement's inner solve: 50 FP32 sweeps with a right-hand side
   at the library's default depth against the oracle's full FP64 run, and the
   FP64 residual and the fused update-and-residual bitwise over the whole grid.
 """
-import concurrent.futures as cf
 import math
 
 import numpy as np
@@ -33,103 +33,108 @@ def dev(u, dtype=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(u)).to("cuda", dtype)
 
 
-def samples():
-    """(i, j, k) array indices of the sampled cells."""
-    rng = np.random.default_rng(123)
-    pts = {(1, 1, 1), (N, N, N), (1, N, 1), (N, 1, N), (N // 2, N // 2, N // 2)}
-    # block edges at depth 4: 64-lane blocks start their valid i ranges at 1,
-    # 60, 116, ..., 508; 72-row blocks (the default) their j ranges at 1, 68,
-    # 132, ..., 452, and 56-row blocks at 1, 52, 100, ..., 484; k chunks of
-    # 2, 3 or 5 per column meet near 257, 172 / 343 and 103 / 206 / ...
-    for i in (59, 60, 115, 116, 507, 508):
-        pts.add((i, int(rng.integers(1, N + 1)), int(rng.integers(1, N + 1))))
-    for j in (67, 68, 131, 132, 451, 452, 51, 52, 483, 484):
-        pts.add((int(rng.integers(1, N + 1)), j, int(rng.integers(1, N + 1))))
-    for k in (256, 257, 171, 172, 342, 343, 103, 104, 2, N - 1):
-        pts.add((int(rng.integers(1, N + 1)), int(rng.integers(1, N + 1)), k))
-    while len(pts) < 48:
-        pts.add(tuple(int(x) for x in rng.integers(1, N + 1, size=3)))
-    return sorted(pts)
-
-
 @pytest.fixture(scope="module")
 def grid512():
+    """(level-0 grid on the host, the oracle's level 100 on the GPU)."""
     u = inputs.grid(N, N, N, seed=0)
-    pts = samples()
-    with cf.ThreadPoolExecutor(max_workers=16) as ex:
-        ref = list(ex.map(lambda p: oracle.point(u, T, *p), pts))
-    return u, pts, np.array(ref)
+    ref = dev(oracle.sweeps(u, T))
+    yield u, ref
+    del ref
+    torch.cuda.empty_cache()
 
 
-def sampled(out, pts):
-    h = out.cpu().numpy()
-    return np.array([h[k, j, i] for i, j, k in pts])
+def same_as(out, ref):
+    """Bitwise equality of two float64 device tensors (no NaN in them)."""
+    return bool(torch.equal(out.view(torch.int64), ref.view(torch.int64)))
 
 
-def test_512_plain_sampled(jac, grid512):
-    u, pts, ref = grid512
+def run_blocked(jac, u, **kw):
+    a = dev(u)
+    b = torch.full_like(a, float("nan"))
+    out = jac.tblock(a, b, T, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_512_plain_full(jac, grid512):
+    u, ref = grid512
     a = dev(u)
     b = torch.full_like(a, float("nan"))
     out = jac.plain(a, b, T)
     torch.cuda.synchronize()
-    assert np.array_equal(sampled(out, pts), ref)
+    assert same_as(out, ref)
 
 
 @pytest.mark.parametrize("t", [1, 2, 3, 4, 5, 6, 8])
-def test_512_blocked_default_sampled(jac, grid512, t):
+def test_512_blocked_default_full(jac, grid512, t):
     """The benchmark's call: jacobi_tblock with the library's default block
-    for depth t (t = 4 is the headline configuration)."""
-    u, pts, ref = grid512
+    for depth t (t = 4 is the headline configuration), every cell."""
+    u, ref = grid512
+    assert same_as(run_blocked(jac, u, t=t), ref)
+
+
+@pytest.mark.parametrize("t", [4, 5])
+def test_512_blocked_every_shape_full(jac, grid512, t):
+    """Every block shape of the menu at the headline depth and the next one
+    (the by-depth figures time them all), every cell."""
+    from paper_0912_4506_amd._lib import JacobiError, JAC_EUNSUPPORTED
+    u, ref = grid512
+    ran = 0
+    for bx, by, w in jac.tile_menu(torch.float64):
+        try:
+            out = run_blocked(jac, u, t=t, bx=bx, by=by, waves=w)
+        except JacobiError as e:
+            assert e.code == JAC_EUNSUPPORTED, e
+            continue
+        assert same_as(out, ref), (t, bx, by, w)
+        ran += 1
+        del out
+    assert ran >= 8
+
+
+@pytest.mark.parametrize("team,t,kchunk", [(2, 4, 32), (1, 4, 128), (4, 2, 64)])
+def test_512_pipelined_full(jac, grid512, team, t, kchunk):
+    """The pipelined schedule at the workload size (the benchmark's best
+    configuration, team 1, t = 4, 128-plane chunks, and two with several
+    passes in flight), every cell."""
+    u, ref = grid512
     a = dev(u)
     b = torch.full_like(a, float("nan"))
-    out = jac.tblock(a, b, T, t=t)
+    plan = jac.PipelinePlan(a, b, T, team=team, t=t, kchunk=kchunk)
+    plan.run("relaxed")
     torch.cuda.synchronize()
-    got = sampled(out, pts)
-    bad = [(p, g, r) for p, g, r in zip(pts, got, ref) if not g == r]
-    assert not bad, bad[:5]
+    assert not plan.wait_error()
+    assert same_as(plan.results()[0], ref)
 
 
-def test_512_pipelined_sampled(jac, grid512):
-    """The pipelined schedule at the workload size (two passes in flight,
-    4 sweeps per item, 32-plane chunks), bitwise at the sampled cells."""
-    u, pts, ref = grid512
-    a = dev(u)
-    b = torch.full_like(a, float("nan"))
-    out = jac.pipelined(a, b, T, team=2, t=4, kchunk=32)
-    torch.cuda.synchronize()
-    assert np.array_equal(sampled(out, pts), ref)
-
-
-def test_512_compressed_sampled(jac, grid512):
-    """The compressed single grid at the workload size (t = 4, the default
-    block), bitwise at the sampled cells of the frame holding level T."""
-    u, pts, ref = grid512
-    arr = torch.empty(jac.compressed_shape(N, N, N, 4), dtype=torch.float64, device="cuda")
-    jac.compressed_frame(arr, 4, 0).copy_(torch.from_numpy(u))
-    run = jac.Compressed(arr, T, 4).run()
+@pytest.mark.parametrize("t", [4, 5])
+def test_512_compressed_full(jac, grid512, t):
+    """The compressed single grid at the workload size (the default block of
+    each depth; t = 5 is the benchmark's best), every cell of the frame
+    holding level T."""
+    u, ref = grid512
+    arr = torch.empty(jac.compressed_shape(N, N, N, t), dtype=torch.float64, device="cuda")
+    jac.compressed_frame(arr, t, 0).copy_(torch.from_numpy(u))
+    run = jac.Compressed(arr, T, t).run()
     torch.cuda.synchronize()
     assert not run.wait_error()
-    assert np.array_equal(sampled(run.result(), pts), ref)
+    res = run.result()
+    assert bool(torch.equal(res, ref))
+    del arr, run, res
+    torch.cuda.empty_cache()
 
 
-@pytest.fixture(scope="module")
-def grid512_f32():
-    u = inputs.grid(N, N, N, seed=0).astype(np.float32).astype(np.float64)
-    pts = samples()[::3]
-    with cf.ThreadPoolExecutor(max_workers=16) as ex:
-        ref = list(ex.map(lambda p: oracle.point(u, T, *p), pts))
-    return u, pts, np.array(ref)
-
-
-def test_512_fp32_blocked_default_sampled(jac, grid512_f32):
-    """FP32 at the workload size with the library's default blocking: within
-    1e-5 of the FP64 oracle run on the FP32-rounded input."""
-    u, pts, ref = grid512_f32
+def test_512_fp32_blocked_default_full(jac):
+    """FP32 at the workload size with the library's default blocking: every
+    cell within 1e-5 of the FP64 oracle run on the FP32-rounded input."""
+    u = inputs.grid(N, N, N, seed=0).astype(np.float32)
+    ref = dev(oracle.sweeps(u.astype(np.float64), T))
     a = dev(u, torch.float32)
     b = torch.empty_like(a)
     out = jac.tblock(a, b, T)
     torch.cuda.synchronize()
-    assert np.max(np.abs(sampled(out, pts).astype(np.float64) - ref)) <= 1e-5
+    err = (out.double() - ref).abs().max().item()
+    assert err <= 1e-5, err
 
 
 def test_768_rhs_fp32_default(jac):

@@ -1,0 +1,59 @@
+"""GPU parity of the D3Q19 lattice Boltzmann steps (lbm_d3q19_steps, through
+the C ABI) with the CPU oracle (oracle/lbm.c, pinned by tests/test_oracle_lbm.py):
+FP64 bitwise (the kernel keeps the oracle's order of operations), FP32
+within 2e-6 of the FP64 oracle on the FP32-rounded input, on ragged boxes
+and at the size the benchmark times."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0912_4506_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def run(jac, f, omega, T, dtype=torch.float64):
+    a = torch.from_numpy(np.ascontiguousarray(f)).to("cuda", dtype)
+    b = torch.full_like(a, float("nan"))
+    out = jac.lbm_d3q19(a, b, omega, T)
+    torch.cuda.synchronize()
+    assert out.data_ptr() == (b.data_ptr() if T % 2 else a.data_ptr())
+    return out.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (7, 5, 4), (64, 4, 3), (65, 33, 17), (130, 9, 12),
+                                   (3, 70, 5)])
+@pytest.mark.parametrize("omega,T", [(1.0, 1), (1.7, 6), (0.6, 5)])
+def test_lbm_fp64_bitwise(jac, shape, omega, T):
+    nx, ny, nz = shape
+    f = inputs.lbm_populations(nx, ny, nz, seed=sum(shape))
+    ref = oracle.lbm_d3q19(f, omega, T)
+    assert np.array_equal(run(jac, f, omega, T), ref)
+
+
+def test_lbm_fp32(jac):
+    f = inputs.lbm_populations(70, 20, 9, seed=5).astype(np.float32)
+    ref = oracle.lbm_d3q19(f.astype(np.float64), 1.3, 8)
+    got = run(jac, f, 1.3, 8, torch.float32)
+    assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
+
+
+def test_lbm_zero_steps_and_streaming_only(jac):
+    """T = 0 leaves f in place; omega = 0 streams only (an exact shift)."""
+    f = inputs.lbm_populations(9, 6, 5, seed=6)
+    assert np.array_equal(run(jac, f, 1.0, 0), f)
+    assert np.array_equal(run(jac, f, 0.0, 3), oracle.lbm_d3q19(f, 0.0, 3))
+
+
+def test_lbm_bench_size_bitwise(jac):
+    """The benchmark's launch (256^3 box, FP64, omega = 1.7), four steps,
+    every population of every cell against the oracle."""
+    n = 256
+    f = inputs.lbm_populations(n, n, n, seed=0)
+    ref = torch.from_numpy(oracle.lbm_d3q19(f, 1.7, 4)).to("cuda")
+    a = torch.from_numpy(f).to("cuda")
+    b = torch.empty_like(a)
+    out = jac.lbm_d3q19(a, b, 1.7, 4)
+    torch.cuda.synchronize()
+    assert bool(torch.equal(out.view(torch.int64), ref.view(torch.int64)))

@@ -1,7 +1,8 @@
 """GPU parity of pipelined temporal blocking (jacobi_pipelined_plan run by
 jacobi_batched_run in relaxed mode) with the CPU oracle: FP64 bitwise, FP32
 within 1e-5, for several team sizes, sweeps per item, k chunks and block
-shapes on ragged grids."""
+shapes on ragged grids, and for several settings of the relaxed
+synchronisation of Eq. 3 (lower distance, upper distance, team delay)."""
 import numpy as np
 import pytest
 import torch
@@ -57,3 +58,28 @@ def test_pipelined_lockstep_refused(jac):
     plan = jac.PipelinePlan(a, torch.empty_like(a), 4, team=2)
     with pytest.raises(JacobiError):
         plan.run("lockstep")
+
+
+@pytest.mark.parametrize("sync", [(1, 1, 0), (1, 2, 0), (1, 4, 0), (2, 3, 0), (1, 2, 8), (3, 0, 2)])
+@pytest.mark.parametrize("shape,T,team,t,kchunk", [
+    ((130, 70, 200), 17, 4, 1, 8),
+    ((70, 45, 97), 12, 3, 2, 6),
+])
+def test_pipelined_relaxed_sync_bitwise(jac, shape, T, team, t, kchunk, sync):
+    """Lock-step (dl = du = 1), loose pipelines (du = 2, 4), a wider lower
+    distance, a team delay: the waits change the pacing only, so every
+    result is bitwise the oracle's, on two runs of one plan."""
+    dl, du, dt = sync
+    u = inputs.grid(*shape, seed=11)
+    ref = oracle.sweeps(u, T)
+    a = dev(u)
+    b = torch.full_like(a, float("nan"))
+    plan = jac.PipelinePlan(a, b, T, team=team, t=t, kchunk=kchunk, dl=dl, du=du, dt=dt)
+    for rep in range(2):
+        if rep:
+            a.copy_(dev(u))
+            b.fill_(float("nan"))
+        plan.run("relaxed")
+        torch.cuda.synchronize()
+        assert not plan.wait_error(), (sync, rep)
+        assert np.array_equal(plan.results()[0].cpu().numpy(), ref), (sync, rep)

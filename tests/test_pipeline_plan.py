@@ -1,15 +1,20 @@
 """The pipelined schedule's plan image, on the CPU (jacobi_pipelined_plan
 only writes host memory): every (pass, block) appears once, and every block
-an item waits on (the 27 neighbours of the previous pass) comes earlier in
-the item order -- the condition that keeps relaxed-mode waits from
-deadlocking.  The pass-by-pass order of a one-grid batch is checked too."""
+an item waits on comes earlier in the item order -- the condition that keeps
+relaxed-mode waits from deadlocking, since persistent workgroups take items
+in order and every earlier item is held by a running workgroup.  The waits
+are those of the batched kernel: the 27 neighbours of the previous pass, and
+for pipelined runs the two conditions of Eq. 3 (the previous pass's chunk
+tk + dl, plus the team delay dt at a segment's front; the next pass's chunk
+tk - du - 2, except at a segment's rear).  The pass-by-pass order of a
+one-grid batch is checked too."""
 import ctypes
 import struct
 
 import pytest
 
 from paper_0912_4506_amd import _lib
-from paper_0912_4506_amd._lib import Grid, Tile, JAC_EARG
+from paper_0912_4506_amd._lib import Grid, Pipeline, Tile, JAC_EARG
 
 
 @pytest.fixture(scope="module")
@@ -18,7 +23,7 @@ def lib():
 
 
 HDR = struct.Struct("<I9i5q")           # magic, dtype .. team, grids_off .. max_shell
-GRID = struct.Struct("<QQqq12i")        # a, b, sy, sz, nx .. counter_off
+GRID = struct.Struct("<QQqq16i")        # a, b, sy, sz, nx .. counter_off, team, dl, du, dt
 
 
 def parse(buf):
@@ -28,11 +33,13 @@ def parse(buf):
     grids_off, items_off = h[10], h[11]
     g = GRID.unpack_from(raw, grids_off)
     nti, ntj, nkc, passes = g[7], g[8], g[9], g[13]
+    gteam, dl, du, dt = g[16], g[17], g[18], g[19]
     items = [struct.unpack_from("<4i", raw, items_off + 16 * n)[:3] for n in range(nitems)]
-    return dict(order=order, team=team, nti=nti, ntj=ntj, nkc=nkc, passes=passes, items=items)
+    return dict(order=order, team=team, nti=nti, ntj=ntj, nkc=nkc, passes=passes, items=items,
+                gteam=gteam, dl=dl, du=du, dt=dt)
 
 
-def plan(lib, shape, T, team, t, kchunk, bx=64, by=72, waves=12, dtype=1):
+def plan(lib, shape, T, team, t, kchunk, bx=64, by=72, waves=12, dtype=1, sync=None):
     nx, ny, nz = shape
     g = Grid(nx, ny, nz, 0, 0)
     tile = Tile(t, bx, by, kchunk, waves)
@@ -40,10 +47,34 @@ def plan(lib, shape, T, team, t, kchunk, bx=64, by=72, waves=12, dtype=1):
     assert n > 0, lib.jacobi_last_error()
     buf = (ctypes.c_ubyte * n)()
     out = (ctypes.c_int * 1)()
+    sy = ctypes.byref(Pipeline(*sync)) if sync else None
     rc = lib.jacobi_pipelined_plan(dtype, ctypes.byref(g), ctypes.c_void_p(1 << 20),
-                                   ctypes.c_void_p(1 << 34), T, team, ctypes.byref(tile), buf, n, out)
+                                   ctypes.c_void_p(1 << 34), T, team, sy, ctypes.byref(tile), buf, n,
+                                   out)
     assert rc == 0, lib.jacobi_last_error()
     return parse(buf), out[0], buf
+
+
+def waits(p, pas, tile):
+    """(pass, tile) pairs the batched kernel makes item (pas, tile) wait on."""
+    nti, ntj, nkc, team = p["nti"], p["ntj"], p["nkc"], p["gteam"]
+    ti, tj, tk = tile % nti, tile // nti % ntj, tile // (nti * ntj)
+    out = []
+    if pas > 0:
+        for dk in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    a, b, c = ti + di, tj + dj, tk + dk
+                    if 0 <= a < nti and 0 <= b < ntj and 0 <= c < nkc:
+                        out.append((pas - 1, (c * ntj + b) * nti + a))
+    if team > 0 and pas > 0:
+        c = min(tk + p["dl"] + (p["dt"] if pas % team == 0 else 0), nkc - 1)
+        out.append((pas - 1, (c * ntj + tj) * nti + ti))
+    if team > 0 and p["du"] > 0 and pas % team != team - 1 and pas + 1 < p["passes"]:
+        c = tk - p["du"] - 2
+        if c >= 0:
+            out.append((pas + 1, (c * ntj + tj) * nti + ti))
+    return out
 
 
 def check_order(p):
@@ -55,15 +86,8 @@ def check_order(p):
     nti, ntj, nkc = p["nti"], p["ntj"], p["nkc"]
     assert len(pos) == p["passes"] * nti * ntj * nkc
     for (pas, tile), n in pos.items():
-        if pas == 0:
-            continue
-        ti, tj, tk = tile % nti, tile // nti % ntj, tile // (nti * ntj)
-        for dk in (-1, 0, 1):
-            for dj in (-1, 0, 1):
-                for di in (-1, 0, 1):
-                    a, b, c = ti + di, tj + dj, tk + dk
-                    if 0 <= a < nti and 0 <= b < ntj and 0 <= c < nkc:
-                        assert pos[(pas - 1, (c * ntj + b) * nti + a)] < n
+        for dep in waits(p, pas, tile):
+            assert pos[dep] < n, ((pas, tile), dep)
 
 
 @pytest.mark.parametrize("shape,T,team,t,kchunk", [
@@ -79,7 +103,7 @@ def test_pipelined_order_respects_dependencies(lib, shape, T, team, t, kchunk):
     assert p["passes"] == -(-T // t) and out_idx == p["passes"] % 2
     assert p["nkc"] == -(-shape[2] // kchunk)
     check_order(p)
-    # within a segment, pass seg+s runs s chunks behind pass seg: the first
+    # within a segment, pass seg+s runs 2s chunks behind pass seg (dl = 1): the first
     # item of a later pass of the segment comes after its predecessor's item
     # on the next chunk
     firsts = {}
@@ -112,11 +136,11 @@ def test_pipelined_argument_checks(lib):
     out = (ctypes.c_int * 1)()
     for team in (0, -3, 2000):
         assert lib.jacobi_pipelined_plan(1, ctypes.byref(g), ctypes.c_void_p(1 << 20),
-                                         ctypes.c_void_p(1 << 34), 10, team, ctypes.byref(tile),
-                                         buf, n, out) == JAC_EARG
+                                         ctypes.c_void_p(1 << 34), 10, team, None,
+                                         ctypes.byref(tile), buf, n, out) == JAC_EARG
     assert lib.jacobi_pipelined_plan(1, ctypes.byref(g), ctypes.c_void_p(1 << 20),
-                                     ctypes.c_void_p(1 << 34), 10, 2, ctypes.byref(tile), buf, n - 16,
-                                     out) != 0
+                                     ctypes.c_void_p(1 << 34), 10, 2, None, ctypes.byref(tile), buf,
+                                     n - 16, out) != 0
     # a pipelined plan refuses lockstep runs before any HIP call
     p, _, buf = plan(lib, (40, 40, 40), 10, 2, 1, 8)
     ws = lib.jacobi_batched_workspace(buf)
@@ -124,3 +148,55 @@ def test_pipelined_argument_checks(lib):
     rc = lib.jacobi_batched_run(buf, ctypes.c_void_p(1 << 36), ctypes.c_void_p(1 << 38), ws,
                                 _lib.JAC_BATCH_LOCKSTEP, None)
     assert rc == JAC_EARG and "relaxed" in lib.jacobi_last_error().decode()
+
+
+@pytest.mark.parametrize("sync", [(1, 1, 0), (1, 2, 0), (1, 4, 0), (1, 0, 0), (2, 2, 0), (2, 5, 3),
+                                  (1, 1, 8), (3, 0, 8)])
+@pytest.mark.parametrize("shape,T,team,t,kchunk", [
+    ((200, 150, 120), 13, 4, 1, 16),
+    ((130, 70, 64), 20, 7, 1, 4),
+    ((64, 64, 33), 9, 3, 3, 5),
+    ((130, 70, 300), 24, 6, 2, 8),
+])
+def test_relaxed_sync_waits_can_end(lib, shape, T, team, t, kchunk, sync):
+    """Both conditions of Eq. 3 (lower distance dl, upper distance du, team
+    delay dt): every counter an item waits on belongs to an earlier item, so
+    every wait ends; the wavefront lag between consecutive passes of a
+    segment is dl + 1 chunks."""
+    p, _, _ = plan(lib, shape, T, team, t, kchunk, sync=sync)
+    assert (p["dl"], p["du"], p["dt"], p["gteam"]) == (*sync, team)
+    check_order(p)
+    nij = p["nti"] * p["ntj"]
+    first = {}
+    for n, (_, pas, tile) in enumerate(p["items"]):
+        first.setdefault((pas, tile // nij), n)
+    lag = sync[0] + 1
+    for pas in range(1, p["passes"]):
+        if pas % team == 0:
+            continue
+        for q in range(p["nkc"] - lag):
+            # pass pas on chunk q goes out with pass pas-1 on chunk q + lag
+            assert first[(pas - 1, q + lag)] < first[(pas, q)]
+
+
+def test_relaxed_sync_argument_checks(lib):
+    g = Grid(40, 40, 40, 0, 0)
+    tile = Tile(1, 64, 72, 8, 12)
+    n = lib.jacobi_pipelined_plan_bytes(1, ctypes.byref(g), 10, ctypes.byref(tile))
+    buf = (ctypes.c_ubyte * n)()
+    out = (ctypes.c_int * 1)()
+    for bad in [(0, 0, 0), (2, 1, 0), (1, 0, -1), (-1, 3, 0)]:
+        rc = lib.jacobi_pipelined_plan(1, ctypes.byref(g), ctypes.c_void_p(1 << 20),
+                                       ctypes.c_void_p(1 << 34), 10, 2,
+                                       ctypes.byref(Pipeline(*bad)), ctypes.byref(tile), buf, n, out)
+        assert rc == JAC_EARG, bad
+    # a plain batch carries no pipeline distances
+    T = (ctypes.c_int * 1)(7)
+    nb = lib.jacobi_batched_plan_bytes(1, 1, ctypes.byref(g), T, ctypes.byref(tile))
+    bb = (ctypes.c_ubyte * nb)()
+    A = (ctypes.c_void_p * 1)(1 << 20)
+    B = (ctypes.c_void_p * 1)(1 << 34)
+    assert lib.jacobi_batched_plan(1, 1, ctypes.byref(g), A, B, T, ctypes.byref(tile), bb, nb,
+                                   out) == 0
+    p = parse(bb)
+    assert (p["gteam"], p["du"], p["dt"]) == (0, 0, 0)
