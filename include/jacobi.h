@@ -289,6 +289,22 @@ int jacobi_update_residual_f64(const jac_grid_t *g, const double *x,
                                size_t ws_bytes, void *stream);
 int jacobi_update_f64(const jac_grid_t *g, double *x, const float *e32,
                       void *stream);
+
+/* jacobi_residual_f64 without a workspace, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as jacobi_residual_f64
+ * (bitwise: the same kernels), but the per-block partial sums of the norm go
+ * to a fixed array of 2^17 doubles (1 MiB) that the library holds on each GPU
+ * it runs on until the process ends.  The call allocates nothing and calls no
+ * allocating routine.  Grids needing more partial sums,
+ * ceil(nx/256) * ceil(ny/8) * ceil(nz/64) > 2^17 (e.g. beyond 2048^3), are
+ * refused with JAC_EUNSUPPORTED before anything is enqueued.  Every call on
+ * one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams, or host threads) race and must be ordered by the
+ * caller; consecutive calls on one stream are safe (each call writes every
+ * partial sum it reads). */
+int jacobi_residual_f64_noalloc(const jac_grid_t *g, const double *x, float *r32,
+                                double *norm2, void *stream);
 int jacobi_fill(int dtype, const jac_grid_t *g, void *x, double value,
                 void *stream);
 

@@ -61,6 +61,7 @@ SIGNATURES = {
     "jacobi_residual_workspace": ([_GP], ctypes.c_size_t),
     "jacobi_residual_f64": ([_GP, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "jacobi_update_f64": ([_GP, _P, _P, _P], ctypes.c_int),
+    "jacobi_residual_f64_noalloc": ([_GP, _P, _P, _P, _P], ctypes.c_int),
     "jacobi_update_residual_f64": ([_GP, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
                                    ctypes.c_int),
     "jacobi_fill": ([ctypes.c_int, _GP, _P, ctypes.c_double, _P], ctypes.c_int),

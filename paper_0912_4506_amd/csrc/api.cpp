@@ -965,6 +965,33 @@ int jacobi_residual_f64(const jac_grid_t *g, const double *x, float *r32, double
     return e == hipSuccess ? JAC_OK : hip_fail(e, "residual launch");
 }
 
+int jacobi_residual_f64_noalloc(const jac_grid_t *g, const double *x, float *r32, double *norm2,
+                                void *stream)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_grid(g, &geo)) || (rc = check_ptr(x, JAC_F64, "x")) ||
+        (rc = check_ptr(r32, JAC_F32, "r32")) || (rc = check_ptr(norm2, JAC_F64, "norm2")))
+        return rc;
+    const size_t xb = (size_t)geo.span * 8, rb = (size_t)geo.span * 4;
+    if (overlap(x, xb, r32, rb) || overlap(norm2, 8, x, xb) || overlap(norm2, 8, r32, rb))
+        return fail(JAC_EARG, "x, r32 and norm2 must not overlap");
+    const int64_t need = jac::residual_partials_plain(grid_args(geo));
+    if (need > jac::noalloc_partials_max())
+        return fail(JAC_EUNSUPPORTED,
+                    "the grid needs %lld partial sums; the allocation-free residual holds at most "
+                    "%lld (ceil(nx/256) * ceil(ny/8) * ceil(nz/64)); use jacobi_residual_f64 with "
+                    "a workspace",
+                    (long long)need, (long long)jac::noalloc_partials_max());
+    double *partial = nullptr;
+    hipError_t e = jac::noalloc_scratch(&partial);
+    if (e != hipSuccess)
+        return hip_fail(e, "scratch address");
+    e = jac::launch_residual(x, r32, partial, norm2, grid_args(geo), (hipStream_t)stream);
+    return e == hipSuccess ? JAC_OK : hip_fail(e, "residual launch");
+}
+
 int jacobi_update_residual_f64(const jac_grid_t *g, const double *x, const float *e32,
                                double *x_new, float *r32, float *zero32, double *norm2, void *ws,
                                size_t ws_bytes, void *stream)

@@ -179,6 +179,13 @@ hipError_t launch_residual(const double *x, float *r32, double *partial, double 
 hipError_t launch_update_residual(const double *x, const float *e32, double *xnew, float *z,
                                   float *r32, double *partial, double *norm2, const GridArgs &g,
                                   hipStream_t st);
+// The allocation-free residual: partial sums go to a fixed device array
+// (noalloc_partials_max() doubles per GPU); noalloc_scratch gives its device
+// address for the current device; residual_partials_plain(g) is how many
+// partial sums launch_residual writes for grid g.
+int64_t noalloc_partials_max();
+int64_t residual_partials_plain(const GridArgs &g);
+hipError_t noalloc_scratch(double **out);
 template <typename real>
 hipError_t launch_grid_fill(real *x, real v, const GridArgs &g, hipStream_t st);
 hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStream_t st);

@@ -12,6 +12,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "device_common.h"
 #include "kernels.h"
@@ -667,6 +668,50 @@ int64_t residual_partials(const GridArgs &g)
 {
     const dim3 d = residual_grid(g, FUSED_RB);  // the larger of the two grids
     return (int64_t)d.x * d.y * d.z;
+}
+
+// ------------------------------------------------ allocation-free residual --
+// Device memory of jacobi_residual_f64_noalloc: the per-block partial sums of
+// the residual norm, in a fixed array instead of a caller's workspace.  Each
+// GPU the library runs on holds its own copy until the process ends.  In host
+// code `scratch` names a host-side stand-in, not the device array: the device
+// address comes from hipGetSymbolAddress, once per device, and only that
+// address is passed to kernels.
+constexpr int64_t kNoAllocPartials = int64_t(1) << 17;  // 1 MiB of doubles
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices];  // device address of `scratch`, per device
+}  // namespace
+
+int64_t noalloc_partials_max() { return kNoAllocPartials; }
+
+int64_t residual_partials_plain(const GridArgs &g)
+{
+    const dim3 d = residual_grid(g, RES_RB);
+    return (int64_t)d.x * d.y * d.z;
+}
+
+hipError_t noalloc_scratch(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;  // looked up with device `dev` current
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch_dev[dev] = (double *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
 }
 
 static hipError_t sum_partials(const double *partial, const dim3 &grid, double *norm2,

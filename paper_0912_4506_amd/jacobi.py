@@ -165,6 +165,20 @@ def residual_f64(x, r32, norm2, ws=None):
     return norm2
 
 
+def residual_f64_noalloc(x, r32, norm2):
+    """residual_f64 with no workspace (jacobi_residual_f64_noalloc): the
+    library's fixed per-GPU array holds the partial sums; nothing is
+    allocated.  Calls that overlap in time on one GPU race."""
+    if x.dtype != torch.float64 or r32.dtype != torch.float32 or norm2.dtype != torch.float64:
+        raise TypeError("residual_f64_noalloc needs float64 x, float32 r32 and a float64 norm2")
+    if x.shape != r32.shape or x.stride() != r32.stride():
+        raise ValueError("x and r32 must share shape and strides")
+    with torch.cuda.device(x.device):
+        check(_lib.load().jacobi_residual_f64_noalloc(ctypes.byref(grid_of(x)), _ptr(x), _ptr(r32),
+                                                      _ptr(norm2), _stream(x)))
+    return norm2
+
+
 def update_f64(x, e32):
     """x += (double)e32 on the interior."""
     if x.dtype != torch.float64 or e32.dtype != torch.float32:

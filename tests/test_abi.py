@@ -190,3 +190,13 @@ def test_lbm_argument_checks(lib):
     assert call(dtype=3) == JAC_EARG
     OUT.value = 5
     assert call(T=0) == 0 and OUT.value == 0
+
+
+def test_noalloc_residual_refuses_large_grids(lib):
+    """More partial sums than the fixed array holds: refused before any HIP call."""
+    g = Grid(16384, 2048, 4096, 0, 0)       # 64 * 256 * 64 partial sums > 2^17
+    rc = lib.jacobi_residual_f64_noalloc(ctypes.byref(g), P(1 << 44), P(1 << 46), P(1 << 20), None)
+    assert rc == JAC_EUNSUPPORTED and "partial sums" in err(lib)
+    rc = lib.jacobi_residual_f64_noalloc(ctypes.byref(Grid(8, 8, 8, 0, 0)), P(1 << 20), P(1 << 20),
+                                         P(1 << 30), None)
+    assert rc == JAC_EARG and "overlap" in err(lib)
