@@ -19,7 +19,8 @@ Other workloads (--workload): `batched` (64 grids, edges log-uniform in
 [32, 256], T = 50, one persistent launch), `adjoint` (256^3, T = 32, t = 8,
 forward + backward), `refine` (768^3 Laplace solve, FP32 inner / FP64 outer,
 vs all-FP64 Jacobi; runs many minutes), `pipelined` (512^3, T = 100, by the
-pipelined schedule), `compressed` (512^3, T = 100, in one array).
+pipelined schedule, with the looseness sweep of Eq. 3), `compressed` (512^3,
+T = 100, in one array), `lbm` (D3Q19 lattice Boltzmann, 256^3, FP64 and FP32).
 """
 import argparse
 import json
@@ -494,13 +495,61 @@ def bench_refine(args):
     return out
 
 
+def bench_lbm(args):
+    """D3Q19 lattice Boltzmann (BGK, periodic 256^3 box, omega = 1.7): the
+    fused pull stream-collide kernel, FP64 and FP32, against its HBM roofline
+    (19 populations read and written per cell update)."""
+    import torch
+    from paper_0912_4506_amd import inputs, jacobi as jac
+
+    n, T = args.lbm_n, args.lbm_steps
+    cells = n ** 3
+    res = {}
+    for dt, name in ((torch.float64, "f64"), (torch.float32, "f32")):
+        f = torch.from_numpy(inputs.lbm_populations(n, n, n, seed=0)).to("cuda", dt)
+        g = torch.empty_like(f)
+        state = {"f": f, "g": g}
+
+        def step():
+            out = jac.lbm_d3q19(state["f"], state["g"], 1.7, T)
+            if out is state["g"]:
+                state["f"], state["g"] = state["g"], state["f"]
+
+        ms = time_steps(step, args.steps, args.warmup)
+        bpl = 2 * 19 * f.element_size()
+        lups = cells * T / (ms * 1e-3)
+        achieved = lups * bpl / 1e9
+        res[name] = {"glups": round(lups / 1e9, 3), "ms_per_step": round(ms, 3),
+                     "kernel_ms": round(ms / T, 4), "bytes_per_lup": bpl,
+                     "achieved_gbs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        del f, g, state
+        torch.cuda.empty_cache()
+    ms_copy = copy_bandwidth(jac)
+    for r in res.values():
+        r["frac_of_copy"] = round(r["achieved_gbs"] / ms_copy, 4)
+    f64 = res["f64"]
+    return {"metric": f"GLUP/s, D3Q19 lattice Boltzmann {n}^3 periodic box, BGK", "unit": "GLUP/s",
+            "value": f64["glups"], "higher_is_better": True, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": f64["ms_per_step"], "dtype": "f64",
+            "data": "synthetic: populations (1 + 0.1 U[0,1)) / 19, numpy default_rng(0)",
+            "config": {"workload": f"D3Q19 BGK {n}^3, omega 1.7, {T} steps per step", "block": [64, 4]},
+            "roofline": {"bound": "hbm", "achieved": f64["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": f64["frac"], "traffic": None,
+                         "algorithmic_bytes_per_lup": f64["bytes_per_lup"]},
+            "by_dtype": res, "copy_bandwidth_gbs": round(ms_copy, 1),
+            "t2_blocked": "refused: 19 populations per cell and level; a 64x8 FP64 block at t = 2 "
+                          "needs about 300 KB of LDS for two levels' plane windows (160 KB exist) "
+                          "and keeps 47% of its columns valid; the largest block that fits (32x8, "
+                          "FP32) would move at most 18% fewer bytes while recomputing 2.3x the cells"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="metric",
-                    choices=["metric", "batched", "adjoint", "refine", "pipelined", "compressed"])
+                    choices=["metric", "batched", "adjoint", "refine", "pipelined", "compressed", "lbm"])
     ap.add_argument("--autotune", action="store_true",
                     help="let the library's autotuner pick the blocking first")
     ap.add_argument("--tmax", type=int, default=8, help="deepest blocking depth the autotuner tries")
@@ -524,6 +573,8 @@ def main():
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--skip-f64", action="store_true")
+    ap.add_argument("--lbm-n", type=int, default=256)
+    ap.add_argument("--lbm-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the library has no "
@@ -532,7 +583,7 @@ def main():
     ensure_built()
     fn = {"metric": bench_metric, "batched": bench_batched, "adjoint": bench_adjoint,
           "refine": bench_refine, "pipelined": bench_pipelined,
-          "compressed": bench_compressed}[args.workload]
+          "compressed": bench_compressed, "lbm": bench_lbm}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 
