@@ -34,12 +34,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# (t, bx, by, waves) -> measured HBM GB per launch of the blocked kernel at
-# 512^3 FP64 (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales the
-# 2 GiB copy gives; profiles/tblock_f64_t4_64x72_512cubed.md)
-MEASURED_TRAFFIC_GB = {(4, 64, 72, 12): 2.317}
-# the same for the compressed-grid kernel (profiles/compressed_f64_t5_512cubed.md)
-COMPRESSED_TRAFFIC_GB = {(5, 64, 56, 8): 2.682}
+# MI355X: 256 CUs at up to 2.4 GHz; one 64-lane VALU instruction per CU and
+# clock (FP64 FMA included: 78.6 TFLOP/s); LDS 128 B per CU and clock
+CUS, CLOCK_HZ = 256, 2.4e9
+LDS_PEAK_TBS = CUS * CLOCK_HZ * 128 / 1e12
+# bytes per lane and LDS instruction of the blocked pass's stream step (its
+# loop issues 16 ds_read_b64, 8 ds_read2st64_b64 and 4 ds_write2st64_b64:
+# 320 B per lane over 28 instructions)
+LDS_BYTES_PER_LANE_INST = 320 / 28
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def profile_figures(name, kernel_fragment):
+    """Figures of a committed rocprofv3 summary (profiles/NAME.md) when it was
+    measured on this kernel instance with the current kernel sources, else
+    None (the kernel changed since the counters were taken)."""
+    from paper_0912_4506_amd import profiling
+    fig = profiling.read_figures(os.path.join(PROFILES, name))
+    if not fig or kernel_fragment not in str(fig.get("kernel", "")):
+        return None
+    if fig.get("kernel_source_sha") != profiling.kernel_source_hash():
+        return None
+    return fig
 METRIC = "GLUP/s & % roofline, 512³ FP64 Jacobi T=100: temporal-blocked vs plain"
 # why a depth the workload names has no kernel
 DEPTH_REFUSAL = {16: " (the blocked pass keeps about two values per cell and level in "
@@ -105,11 +121,18 @@ def cpu_baseline(u, T, lups_per_sweep, target_s=12.0):
     oracle.sweeps(u, 1, nthreads=1)
     dt1 = max((t2 - t1) - (time.perf_counter() - t2), 1e-6)
     oracle.max_threads(cores)     # the oracle's thread count is process-wide: restore it
+    # the paper's baseline model on the host (Eq. 2): P0 = M_s / 16 B with the
+    # host's own copy bandwidth
+    ms_host = oracle.copy_bandwidth(1 << 27, 5)
     n = round(u.shape[0] - 2)
-    return {"value": round(lups_per_sweep * sweeps / dt / 1e9, 4), "unit": "GLUP/s",
+    value = lups_per_sweep * sweeps / dt / 1e9
+    return {"value": round(value, 4), "unit": "GLUP/s",
             "cores": cores, "kind": "oracle",
             "sample": f"{n}^3 FP64 grid, {sweeps} of the {T} sweeps, one run ({dt:.1f} s)",
-            "single_thread": round(lups_per_sweep / dt1 / 1e9, 4)}
+            "single_thread": round(lups_per_sweep / dt1 / 1e9, 4),
+            "host_copy_gbs": round(ms_host / 1e9, 1),
+            "p0_host_glups": round(ms_host / 16 / 1e9, 3),
+            "frac_of_p0_host": round(value / (ms_host / 16 / 1e9), 3)}
 
 
 def bench_metric(args):
@@ -180,15 +203,44 @@ def bench_metric(args):
     torch.cuda.empty_cache()
     ms_copy = copy_bandwidth(jac)
     achieved = cell_bytes / (kernel_ms * 1e-3) / 1e9
-    # HBM traffic per launch of the blocked kernel, from the rocprofv3 PMC runs
-    # summarised in profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales
-    # the 2 GiB copy kernel gives); only for the kernel those runs measured
-    traffic = MEASURED_TRAFFIC_GB.get((t, bx, by, w))
+    glups = lups / (ms * 1e-3) / 1e9
+    # the kernel instance this blocking runs, and its committed profile
+    # (rocprofv3 FETCH_SIZE/WRITE_SIZE scaled by the copy kernel's, and the SQ
+    # instruction counters), used only while the kernel sources are unchanged
+    inst = f"tblock_kernel<double, {t}, {bx // 64}, {by // w}, {w}, 0>"
+    prof_name = f"tblock_f64_t{t}_{bx}x{by}_512cubed.md"
+    fig = profile_figures(prof_name, inst)
+    traffic = fig.get("traffic_gb_per_launch") if fig else None
     if args.traffic:
         traffic = float(args.traffic)
+    from paper_0912_4506_amd import perf_model
+    t_eff = perf_model.t_eff(T, t)
+    p_t = perf_model.roofline(ms_copy * 1e9, T, t) / 1e9          # M_s t_eff / 16 B (Eq. 2)
+    lups_launch = N ** 3 * t_eff
+    secondary = {"p_t": {"t_eff": t_eff, "ms_gbs": round(ms_copy, 1), "glups": round(p_t, 1),
+                         "frac": round(glups / p_t, 4)}}
+    # Eq. 5 as a prediction: speedup over P0 of t_eff updates per transfer when
+    # the levels share an on-chip path of rate M_c' (the LDS bandwidth here;
+    # on a GPU the chip saturates HBM, so M_s,1 = M_s)
+    sp = perf_model.speedup(ms_copy, ms_copy, LDS_PEAK_TBS * 1e3, t_eff)
+    secondary["eq5"] = {"mc_prime_tbs": round(LDS_PEAK_TBS, 1), "speedup_over_p0": round(sp, 3),
+                        "predicted_glups": round(sp * ms_copy / 16, 1),
+                        "measured_over_predicted": round(glups / (sp * ms_copy / 16), 3)}
+    if fig and "sq_insts_valu_per_launch" in fig:
+        valu = fig["sq_insts_valu_per_launch"]
+        per_lup = valu * 64 / lups_launch                           # lane instructions per update
+        ceiling = CUS * CLOCK_HZ * 64 / per_lup / 1e9
+        secondary["valu"] = {"wave_insts_per_launch": int(valu), "lane_insts_per_lup": round(per_lup, 2),
+                             "ceiling_glups": round(ceiling, 1), "frac": round(glups / ceiling, 4),
+                             "peak": "256 CUs x 64 lanes x 2.4 GHz"}
+    if fig and "sq_insts_lds_per_launch" in fig:
+        lds_bytes = fig["sq_insts_lds_per_launch"] * 64 * LDS_BYTES_PER_LANE_INST
+        lds_tbs = lds_bytes / (kernel_ms * 1e-3) / 1e12
+        secondary["lds"] = {"bytes_per_launch": int(lds_bytes), "achieved_tbs": round(lds_tbs, 2),
+                            "peak_tbs": round(LDS_PEAK_TBS, 1), "frac": round(lds_tbs / LDS_PEAK_TBS, 4)}
     line = {
         "metric": METRIC,
-        "value": round(lups / (ms * 1e-3) / 1e9, 2),
+        "value": round(glups, 2),
         "unit": "GLUP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -205,7 +257,11 @@ def bench_metric(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_unit": "GB per launch",
-                     "algorithmic_bytes_per_launch": cell_bytes},
+                     "algorithmic_bytes_per_launch": cell_bytes,
+                     "kernel": inst, "profile": ("profiles/" + prof_name) if fig else None,
+                     "profile_median_us": fig.get("median_us") if fig else None,
+                     "bench_us_per_launch": round(kernel_ms * 1e3, 1),
+                     **secondary},
         "plain": plain,
         "by_depth": by_depth,
         "copy_bandwidth_gbs": round(ms_copy, 1),
@@ -229,8 +285,27 @@ def bench_batched(args):
     b = [torch.empty_like(x) for x in a]
     T = 50
     lups = sum(nx * ny * nz for nx, ny, nz in edges) * T
-    (t, bx, by, w), _ = jac.autotune_batch(a, b, [T] * 64, reps=1)
+    if args.t and args.bx:
+        t, bx, by, w = args.t, args.bx, args.by, args.waves
+    else:
+        (t, bx, by, w), _ = jac.autotune_batch(a, b, [T] * 64, reps=1)
     plan = jac.BatchPlan(a, b, [T] * 64, t=t, bx=bx, by=by, waves=w)
+    # cells the blocks compute per valid cell: every pass of a grid streams
+    # nti*bx x ntj*by columns through the planes of each k chunk [k0, k1)
+    # plus depth planes on either side (k from max(k0 - t, 0) to k1 + t - 1)
+    computed = valid = 0
+    per_grid = []
+    for G in plan.geometry():
+        steps = 0
+        for q in range(G["nkc"]):
+            k0 = 1 + q * G["kchunk"]
+            k1 = min(k0 + G["kchunk"], G["nz"] + 1)
+            steps += (k1 + G["t"]) - max(k0 - G["t"], 0)
+        c = G["nti"] * bx * G["ntj"] * by * steps
+        v = G["nx"] * G["ny"] * G["nz"]
+        computed += c * G["passes"]
+        valid += v * G["passes"]
+        per_grid.append(round(c / v, 2))
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -241,26 +316,40 @@ def bench_batched(args):
     with torch.cuda.graph(g):
         plan.run("relaxed")
     ms = time_steps(g.replay, args.steps, args.warmup)
-    lms = time_steps(lambda: plan.run("lockstep"), args.steps, 1)
-    # per-grid plain calls, one after another
-    def seq_plain():
-        for x, y in zip(a, b):
-            jac.plain(x, y, T)
-    pms = time_steps(seq_plain, max(1, args.steps // 2), 1)
-    def seq_tb():
-        for x, y in zip(a, b):
-            jac.tblock(x, y, T, t=t, bx=bx, by=by, waves=w)
-    tms = time_steps(seq_tb, max(1, args.steps // 2), 1)
+    lms = pms = tms = None
+    if not args.relaxed_only:
+        lms = time_steps(lambda: plan.run("lockstep"), args.steps, 1)
+
+        def seq_plain():      # per-grid plain calls, one after another
+            for x, y in zip(a, b):
+                jac.plain(x, y, T)
+        pms = time_steps(seq_plain, max(1, args.steps // 2), 1)
+
+        def seq_tb():
+            for x, y in zip(a, b):
+                jac.tblock(x, y, T, t=t, bx=bx, by=by, waves=w)
+        tms = time_steps(seq_tb, max(1, args.steps // 2), 1)
+    del a, b, plan, g
+    torch.cuda.empty_cache()
+    ms_copy = copy_bandwidth(jac)
+    passes = math.ceil(T / t)
+    achieved = 16 * (lups / T) * passes / (ms * 1e-3) / 1e9     # 16 B per cell and pass
     return {"metric": "batched GLUP/s, 64 grids (edges log-uniform in [32,256]) FP64 T=50",
             "value": round(lups / (ms * 1e-3) / 1e9, 2), "unit": "GLUP/s", "n_gpus": 1,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "copy_bandwidth_gbs": round(ms_copy, 1),
+                         "p_t_glups": round(ms_copy * (T / passes) / 16, 1)},
+            "computed_per_valid_cell": round(computed / valid, 3),
+            "computed_per_valid_cell_by_grid": per_grid,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
             "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "64 cubic grids" if not args.noncubic else "64 non-cubic grids",
                        "interior_cells": int(lups // T), "t": t, "tile_bx_by": [bx, by], "waves": w,
                        "graph": True},
-            "lockstep_glups": round(lups / (lms * 1e-3) / 1e9, 2),
-            "sequential_plain_glups": round(lups / (pms * 1e-3) / 1e9, 2),
-            "sequential_tblock_glups": round(lups / (tms * 1e-3) / 1e9, 2)}
+            "lockstep_glups": round(lups / (lms * 1e-3) / 1e9, 2) if lms else None,
+            "sequential_plain_glups": round(lups / (pms * 1e-3) / 1e9, 2) if pms else None,
+            "sequential_tblock_glups": round(lups / (tms * 1e-3) / 1e9, 2) if tms else None}
 
 
 def bench_adjoint(args):
@@ -403,7 +492,9 @@ def bench_compressed(args):
               f"{rows[-1]['two_grid_tblock_glups']} in two", file=sys.stderr, flush=True)
     best = max(rows, key=lambda r: r["glups"])
     achieved = 16 * N ** 3 / (best["ms_per_step"] / best["passes"] * 1e-3) / 1e9
+    ms_copy = copy_bandwidth(jac)
     return {"metric": "GLUP/s, 512^3 FP64 Jacobi T=100, compressed single grid", "unit": "GLUP/s",
+            "copy_bandwidth_gbs": round(ms_copy, 1),
             "value": best["glups"], "higher_is_better": True, "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms_per_step"],
             "dtype": "f64", "data": "synthetic: uniform [0,1) interior and shell, numpy default_rng(0)",
@@ -411,13 +502,21 @@ def bench_compressed(args):
                        **{k: best[k] for k in ("t", "tile_bx_by", "waves", "passes")}},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": COMPRESSED_TRAFFIC_GB.get((best["t"], *best["tile_bx_by"],
-                                                               best["waves"])),
+                         "traffic": comp_traffic(best),
                          "traffic_unit": "GB per launch",
                          "note": "per pass incl. its plane copies and shell rewrite"},
             "memory_gb": {"compressed": best["memory_gb"],
                           "two_grids": round(2 * 514 ** 3 * 8 / 1e9, 3)},
             "by_depth": rows}
+
+
+def comp_traffic(row):
+    """HBM GB per pass of the compressed-grid kernel from its committed
+    profile, when that profile measured this instance with the current sources."""
+    bx, by = row["tile_bx_by"]
+    inst = f"compressed_kernel<double, {row['t']}, {bx // 64}, {by // row['waves']}, {row['waves']}>"
+    fig = profile_figures(f"compressed_f64_t{row['t']}_512cubed.md", inst)
+    return fig.get("traffic_gb_per_launch") if fig else None
 
 
 def bench_refine(args):
@@ -564,6 +663,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--noncubic", action="store_true")
+    ap.add_argument("--relaxed-only", action="store_true",
+                    help="batched: time the relaxed graph replay only (no lockstep or per-grid runs)")
     ap.add_argument("--refine-n", type=int, default=768)
     ap.add_argument("--refine-tol", type=float, default=1e-10)
     ap.add_argument("--refine-t", type=int, default=8,

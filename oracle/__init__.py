@@ -63,6 +63,8 @@ def _load():
                                         _L, ctypes.c_int, ctypes.POINTER(_L),
                                         ctypes.POINTER(ctypes.c_double)]
     lib.oracle_jacobi_solve.restype = ctypes.c_int
+    lib.oracle_copy_bandwidth.argtypes = [_L, ctypes.c_int, ctypes.c_int]
+    lib.oracle_copy_bandwidth.restype = ctypes.c_double
     lib.oracle_lbm_lattice.argtypes = [np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"),
                                        _dbl_p]
     lib.oracle_lbm_lattice.restype = None
@@ -154,6 +156,15 @@ def jacobi_solve(x0, tol, check_every=50, max_sweeps=10**7, nthreads=0):
     if rc < 0:
         raise ValueError("oracle_jacobi_solve: bad arguments")
     return x, done.value, rel.value, rc == 0
+
+
+def copy_bandwidth(n_doubles=1 << 27, reps=5, nthreads=0):
+    """Host copy bandwidth in bytes/s (read + write), STREAM-COPY style: the
+    M_s of the CPU baseline's Eq. 2 figure (not part of the method)."""
+    bw = _load().oracle_copy_bandwidth(int(n_doubles), int(reps), nthreads)
+    if bw < 0:
+        raise MemoryError("oracle_copy_bandwidth: allocation failed")
+    return bw
 
 
 def lbm_lattice():

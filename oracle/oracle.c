@@ -382,3 +382,53 @@ int oracle_jacobi_solve(long nx, long ny, long nz, double *x, double tol,
         *rel_res = rel;
     return rel <= tol ? 0 : 1;
 }
+
+/*
+ * The host's copy bandwidth M_s (bytes read plus bytes written per second) in
+ * the manner of the STREAM COPY benchmark that Eq. 2 of the paper takes its
+ * memory bandwidth from: b[i] = a[i] over n doubles on all threads (each
+ * thread first touches the part it copies), the best of `reps` timed copies.
+ * Not the method: the CPU baseline's reference figure P0 = M_s / 16 B.
+ * Returns -1 on allocation failure.
+ */
+double oracle_copy_bandwidth(long n, int reps, int nthreads)
+{
+    if (n < 1 || reps < 1)
+        return -1.0;
+    set_threads(nthreads);
+    double *a = malloc((size_t)n * sizeof(double)), *b = malloc((size_t)n * sizeof(double));
+    if (!a || !b) {
+        free(a);
+        free(b);
+        return -1.0;
+    }
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; i++) {
+        a[i] = 1.0;
+        b[i] = 0.0;
+    }
+    double best = 0.0;
+    for (int r = 0; r <= reps; r++) {
+#ifdef _OPENMP
+        const double t0 = omp_get_wtime();
+#endif
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; i++)
+            b[i] = a[i];
+#ifdef _OPENMP
+        const double dt = omp_get_wtime() - t0;
+#else
+        const double dt = 1.0;
+#endif
+        if (r > 0 && dt > 0.0) {      /* the first copy is a warm-up */
+            const double bw = 2.0 * (double)n * sizeof(double) / dt;
+            if (bw > best)
+                best = bw;
+        }
+    }
+    volatile double sink = b[n / 2];
+    (void)sink;
+    free(a);
+    free(b);
+    return best;
+}
