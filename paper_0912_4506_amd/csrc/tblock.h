@@ -512,7 +512,24 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
         }
     };
 
-    for (int n = 0; n < nsteps; ++n) {
+    // A wave all of whose rows lie past the shell row ny+1 (the tail of the
+    // last block along j) computes nothing any output needs: no live row
+    // reads its rows (a live wave's last row next to it is then the shell row
+    // or past it).  It only takes part in the step's barriers, so its SIMD's
+    // issue slots go to the other waves (batches of small grids leave up to
+    // a third of the waves dead).  Wave 0 is never dead: a block starts at or
+    // below row ny.
+    // (Two loops rather than a test inside one: a path around the step
+    // inside the loop makes the compiler keep both sets of carried values.)
+    const bool dead = xj.e + w * R > p.ny + 1;
+    if (dead) {
+        for (int n = 0; n < nsteps; ++n) {
+            if constexpr (!DBUF)
+                __syncthreads();  // the barrier before a live step overwrites its slab
+            __syncthreads();      // the barrier after the slab is written
+        }
+    }
+    for (int n = 0; n < (dead ? 0 : nsteps); ++n) {
         step(kstart + n, QA, QB, CA, CB);
 #pragma unroll
         for (int s = 0; s < TL; ++s)
@@ -702,15 +719,20 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
                                                 FIXED ? TL : depth, xch);
         if (!L.persistent)
             break;
-        // Publish: the item's output stores are agent-scope, so they write
-        // through this XCD's L2; once every wave has seen them complete
-        // (vmcnt 0) they are visible to all XCDs, which an agent-scope release
-        // fence would otherwise ensure by writing back the whole L2.  The
-        // consumer's acquire fence invalidates its own stale lines.
+        // Publish.  The item's output stores are agent-scope, so they write
+        // through this XCD's L2, and every wave waits until its own stores
+        // have completed (vmcnt 0) before the barrier; thread 0 then bumps
+        // the counter with an agent-scope release store, which pairs with the
+        // consumer's agent-scope acquire fence: every store of the item
+        // happens before the barrier, the barrier before the release, so the
+        // consumer that sees the counter also sees the data, by the memory
+        // model and not only by how the hardware orders write-through stores.
+        // (With the data already written through, the release has little
+        // left to write back.)
         __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
         __syncthreads();
         if (threadIdx.x == 0)
-            __hip_atomic_store(cnt + m.tile, m.pass + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(cnt + m.tile, m.pass + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
