@@ -267,6 +267,23 @@ class BatchPlan:
         """True if a relaxed-mode wait gave up (read after synchronising)."""
         return bool(self.ws[-4:].view(torch.int32).item())
 
+    def geometry(self):
+        """Per grid, the plan's block geometry read back from the host image
+        (layout of the plan header and per-grid records in csrc/kernels.h):
+        dicts of nx, ny, nz, block columns nti x ntj, k chunks nkc of kchunk
+        planes, i-halo hi, T, passes and the plan's depth t."""
+        import struct
+        raw = bytes(self._host)
+        hdr = struct.unpack_from("<I9i5q", raw, 0)
+        n, cfg_t, grids_off = hdr[2], hdr[6], hdr[10]
+        out = []
+        for m in range(n):
+            g = struct.unpack_from("<QQqq16i", raw, grids_off + 96 * m)
+            nx, ny, nz, nti, ntj, nkc, hi, kchunk, T, passes = g[4:14]
+            out.append(dict(nx=nx, ny=ny, nz=nz, nti=nti, ntj=ntj, nkc=nkc, hi=hi, kchunk=kchunk,
+                            T=T, passes=passes, t=cfg_t))
+        return out
+
 
 class PipelinePlan(BatchPlan):
     """Pipelined temporal blocking of one grid (jacobi_pipelined_plan): T
