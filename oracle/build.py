@@ -27,5 +27,34 @@ def build(verbose=False):
     return LIB
 
 
+def build_sanitized(verbose=False):
+    """oracle.c and lbm.c with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc), at _build/san/liboracle.so; load it into a process that preloads
+    gcc's libasan and libubsan (sanitizer_runtimes())."""
+    out_dir = os.path.join(os.path.dirname(HERE), "_build", "san")
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "liboracle.so")
+    flags = [f for f in CFLAGS if f != "-O2"] + ["-O1", "-g", "-fsanitize=address,undefined",
+                                                 "-fno-sanitize-recover=undefined",
+                                                 "-fno-omit-frame-pointer"]
+    cmd = ["gcc", *flags, *SRC, "-o", out, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def sanitizer_runtimes():
+    """gcc's shared libasan and libubsan (to preload, in that order)."""
+    out = []
+    for name in ("libasan.so", "libubsan.so"):
+        path = subprocess.run(["gcc", f"-print-file-name={name}"], capture_output=True,
+                              text=True).stdout.strip()
+        if not os.path.isabs(path):
+            raise FileNotFoundError(name)
+        out.append(os.path.realpath(path))
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

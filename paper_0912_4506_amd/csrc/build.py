@@ -68,5 +68,50 @@ def build(verbose=False, jobs=None):
     return OUT
 
 
+# Host sanitizers for the host code of api.cpp (argument checks, plans):
+# each -fsanitize= goes to the host pass only (device code is built as usual)
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(verbose=False):
+    """A copy of the library whose host code (api.cpp) is built with
+    AddressSanitizer and UndefinedBehaviorSanitizer, linked from the kernel
+    objects of the normal build, at _build/san/libjacobi.so.  Load it into a
+    process that preloads the compiler's ASan runtime (asan_runtime())."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        if src == "api.cpp":
+            continue
+        obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+        if not os.path.exists(obj):
+            obj = _compile(src, verbose)
+        objs.append(obj)
+    san_dir = os.path.join(BUILD_DIR, "san")
+    os.makedirs(san_dir, exist_ok=True)
+    api_obj = os.path.join(san_dir, "api.cpp.o")
+    cmd = [HIPCC, *COMMON, "-g", *SANITIZE, "-c", os.path.join(HERE, "api.cpp"), "-o", api_obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compiling api.cpp with sanitizers failed:\n{r.stderr}")
+    out = os.path.join(san_dir, "libjacobi.so")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *SANITIZE, *objs, api_obj, "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"linking the sanitized library failed:\n{r.stderr}")
+    return out
+
+
+def asan_runtime():
+    """The compiler's shared ASan runtime (to preload)."""
+    r = subprocess.run([os.path.join(os.path.dirname(HIPCC), "..", "llvm", "bin", "clang"),
+                        "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise FileNotFoundError("clang's libclang_rt.asan-x86_64.so not found")
+    return os.path.realpath(path)
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build_sanitized(verbose=True) if "--sanitize" in sys.argv else build(verbose="-v" in sys.argv))
