@@ -14,13 +14,14 @@ The only host synchronisation per outer iteration reads |r|^2 (8 bytes).
 """
 import math
 
+import numpy as np
 import torch
 
 from . import jacobi
 
 
 def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, callback=None,
-                 bx=0, by=0, waves=0, fused=True):
+                 bx=0, by=0, waves=0, fused=True, state=None):
     """Solve in place.  x: float64 GPU grid (shell = Dirichlet data, interior
     = initial guess).  Returns (x, outer_iterations, relative_residual).
     ``check_every`` > 1 reads the norm only every that many outer iterations
@@ -30,7 +31,16 @@ def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, ca
     one pass over memory (x then alternates between two buffers, and the
     next inner solve's zero guess is written in the same pass); False runs
     the update, the residual and the zero fill as separate kernels.  Both
-    give bitwise the same iterates."""
+    give bitwise the same iterates.
+
+    ``state``: a dict for checkpoint and resume.  On return it holds
+    ``outer`` (outer iterations done, counted from the original start) and
+    ``r0`` (the residual norm the tolerance is relative to).  Passed back in
+    with those keys, beside the x that run returned, the solve continues
+    where it stopped: the iterates, and so the final x and the outer count,
+    are bitwise those of an uninterrupted run (max_outer counts from the
+    original start too).  save_checkpoint / load_checkpoint keep both on
+    disk."""
     if x.dtype != torch.float64:
         raise TypeError("x must be float64")
     r32 = torch.empty(x.shape, dtype=torch.float32, device=x.device)
@@ -43,9 +53,9 @@ def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, ca
     ws = jacobi.residual_workspace(x)
     xa, xb = x, (x.clone() if fused else None)
     jacobi.residual_f64(xa, r32, norm2, ws)
-    r0 = None
+    r0 = None if state is None else state.get("r0")
     rel = float("inf")
-    it = 0
+    it = 0 if state is None else int(state.get("outer", 0))
     while True:
         if it % check_every == 0 or it >= max_outer:
             n = math.sqrt(norm2.item())
@@ -70,7 +80,23 @@ def refine_solve(x, tol=1e-10, inner=50, t=8, max_outer=10**6, check_every=1, ca
         it += 1
     if xa is not x:
         x.copy_(xa)
+    if state is not None:
+        state.update(outer=it, r0=r0)
     return x, it, rel
+
+
+def save_checkpoint(path, x, state):
+    """Write a stopped refinement (the grid x and its state dict) to an .npz
+    file."""
+    np.savez(path, x=x.detach().cpu().numpy(), outer=np.int64(state["outer"]),
+             r0=np.float64(state["r0"]))
+
+
+def load_checkpoint(path, device="cuda"):
+    """(x on `device`, state) of a checkpoint written by save_checkpoint."""
+    with np.load(path, allow_pickle=False) as f:
+        x = torch.from_numpy(f["x"]).to(device)
+        return x, {"outer": int(f["outer"]), "r0": float(f["r0"])}
 
 
 def jacobi_solve_f64(x, tol=1e-10, check=50, t=None, max_sweeps=10**9, callback=None):

@@ -105,6 +105,30 @@ def test_refine_fused_equals_separate(jac):
     assert torch.equal(xf, xs)
 
 
+@pytest.mark.parametrize("fused,check_every", [(True, 1), (False, 1), (True, 3)])
+def test_refine_resumed_equals_uninterrupted(jac, tmp_path, fused, check_every):
+    """A solve stopped half way (max_outer), written to disk, read back and
+    resumed ends with bitwise the x, the outer count and the relative
+    residual of the run that was never stopped."""
+    from paper_0912_4506_amd.refine import refine_solve, save_checkpoint, load_checkpoint
+    g = inputs.laplace_problem(40, 33, 29, seed=3)
+    kw = dict(tol=1e-9, inner=50, t=5, fused=fused, check_every=check_every)
+    x_full, outer_full, rel_full = refine_solve(dev(g), **kw)
+    assert outer_full >= 4
+    stop = outer_full // 2 + 1
+    st = {}
+    x_half, outer_half, _ = refine_solve(dev(g), max_outer=stop, state=st, **kw)
+    assert outer_half == stop and st["outer"] == stop and st["r0"] > 0
+    path = tmp_path / "refine.npz"
+    save_checkpoint(path, x_half, st)
+    del x_half
+    x2, st2 = load_checkpoint(path, "cuda")
+    assert st2 == st
+    x_res, outer_res, rel_res = refine_solve(x2, state=st2, **kw)
+    assert outer_res == outer_full and rel_res == rel_full and st2["outer"] == outer_full
+    assert torch.equal(x_res, x_full)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_fill_dense_and_strided(jac, dtype):
     # dense grids take the flat path (odd element count: a ragged tail);
