@@ -144,6 +144,16 @@ int jacobi_tblock(int dtype, const jac_grid_t *g, void *a, void *b, int T,
  * of at least jacobi_adjoint_workspace(dtype, g, t) bytes (t as in tile,
  * 0 = library choice), aligned to the element size, not overlapping the grids.
  * T = 0 enqueues nothing: the input is the gradient (*out_idx = 0). */
+/* dst += src on every element of a grid, shell included, one rounding per
+ * element.  It is the step between two adjoint segments when a loss also
+ * depends on an intermediate level s: the gradient arriving at level s is
+ * added to the adjoint of the later levels before the earlier segment runs
+ * (the sweep map is linear, so the adjoint of a sum of losses is the sum of
+ * their adjoints).  dst and src: grids of the same dtype and geometry,
+ * aligned to the element size; they must not overlap unless dst == src. */
+int jacobi_grid_add(int dtype, const jac_grid_t *g, void *dst, const void *src,
+                    void *stream);
+
 size_t jacobi_adjoint_workspace(int dtype, const jac_grid_t *g, int t);
 int jacobi_adjoint(int dtype, const jac_grid_t *g, void *lam_a, void *lam_b,
                    int T, const jac_tile_t *tile, void *ws, size_t ws_bytes,
@@ -320,11 +330,42 @@ int jacobi_copy(void *dst, const void *src, size_t bytes, void *stream);
  * register spills, `reps` timed runs each after one warm-up, on `stream`
  * (synchronising it).  Writes the fastest choice to *best_host (kchunk = 0,
  * library choice) and its time per run in ms to *best_ms_host (may be NULL),
- * and remembers it for the process: later jacobi_tblock calls on the same
- * dtype, geometry and T with t, bx, by all 0 use it. */
+ * and remembers it (see the tuning cache below): later jacobi_tblock calls
+ * on the same device architecture, dtype, geometry and T with t, bx, by all
+ * 0 use it. */
 int jacobi_autotune(int dtype, const jac_grid_t *g, void *a, void *b, int T,
                     int tmax, int reps, jac_tile_t *best_host,
                     float *best_ms_host, void *stream);
+
+/* Tuning choices that outlive the process.  The library keeps the choices of
+ * jacobi_autotune per (GPU architecture, dtype, nx, ny, nz, sy, sz, T); the
+ * architecture is the device's name without feature flags ("gfx950").  A
+ * choice for another architecture is kept but never used.  The cache file is
+ * text, one choice a line, "arch dtype nx ny nz sy sz T t bx by waves kchunk
+ * ms" (dtype f32 or f64; sy, sz as resolved, never 0; ms the measured time
+ * per run), with '#' comment lines.  If the environment names a file in
+ * JACOBI_TUNE_CACHE, the library reads it at its first lookup (a missing
+ * file is no error; one that does not parse is reported on stderr and
+ * ignored) and rewrites it after every successful jacobi_autotune.  Host
+ * only; no HIP call except the one-time device query of the architecture.
+ *  jacobi_tune_save: writes every remembered choice to path, replacing the
+ *    file (through a temporary file in the same directory and a rename).
+ *    JAC_EARG if it cannot be written.
+ *  jacobi_tune_load: adds the choices in path (replacing remembered ones
+ *    with the same key).  A line that does not parse, or names a dtype,
+ *    depth or block shape the library does not have, is an error (JAC_EARG,
+ *    the message names the line) and then nothing from the file is kept.
+ *    *n_loaded (may be NULL) receives the number of choices read.
+ *  jacobi_tune_lookup: the remembered choice for (arch, dtype, g, T) into
+ *    *tile_host, or JAC_EUNSUPPORTED when there is none.  arch NULL: the
+ *    current device's architecture.
+ *  jacobi_tune_forget: forgets every remembered choice (the file, if any, is
+ *    left alone). */
+int jacobi_tune_save(const char *path);
+int jacobi_tune_load(const char *path, int *n_loaded);
+int jacobi_tune_lookup(const char *arch, int dtype, const jac_grid_t *g, int T,
+                       jac_tile_t *tile_host);
+int jacobi_tune_forget(void);
 
 /* Supported block shapes for jacobi_tblock / jacobi_adjoint / batches: writes
  * up to `cap` triples (bx, by, waves) into shapes_host[3*n .. 3*n+2] and

@@ -65,7 +65,12 @@ SIGNATURES = {
     "jacobi_update_residual_f64": ([_GP, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
                                    ctypes.c_int),
     "jacobi_fill": ([ctypes.c_int, _GP, _P, ctypes.c_double, _P], ctypes.c_int),
+    "jacobi_grid_add": ([ctypes.c_int, _GP, _P, _P, _P], ctypes.c_int),
     "jacobi_copy": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "jacobi_tune_save": ([ctypes.c_char_p], ctypes.c_int),
+    "jacobi_tune_load": ([ctypes.c_char_p, _IP], ctypes.c_int),
+    "jacobi_tune_lookup": ([ctypes.c_char_p, ctypes.c_int, _GP, ctypes.c_int, _TP], ctypes.c_int),
+    "jacobi_tune_forget": ([], ctypes.c_int),
     "jacobi_batched_plan_bytes": ([ctypes.c_int, ctypes.c_int, _GP, _IP, _TP], ctypes.c_size_t),
     "jacobi_batched_plan": ([ctypes.c_int, ctypes.c_int, _GP, ctypes.POINTER(_P),
                              ctypes.POINTER(_P), _IP, _TP, _P, ctypes.c_size_t, _IP], ctypes.c_int),

@@ -15,8 +15,9 @@ checkpoints(u, T, every, depth=None)
                                      forward keeps those levels; the backward
                                      runs one adjoint segment per interval and
                                      adds the gradient arriving at a checkpoint
-                                     when it reaches that level, so losses on
-                                     intermediate levels work.
+                                     when it reaches that level (in the
+                                     library), so losses on intermediate
+                                     levels work.
 """
 import torch
 
@@ -73,7 +74,10 @@ class _Checkpoints(torch.autograd.Function):
         lam = None
         for g, d in zip(reversed(grads), reversed(ctx.segments)):
             if g is not None:
-                lam = g.clone() if lam is None else lam + g
+                if lam is None:
+                    lam = g.detach().clone(memory_format=torch.contiguous_format)
+                else:
+                    lam = jacobi.grid_add(lam, g.detach().contiguous())
             if lam is not None:
                 lam = _adjoint(lam, d, ctx.depth)
         return lam, None, None, None

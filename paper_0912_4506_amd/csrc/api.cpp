@@ -6,6 +6,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cctype>
 #include <climits>
 #include <cstdarg>
 #include <cstdint>
@@ -16,6 +17,10 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <utility>
+#include <vector>
+
+#include <unistd.h>
 
 #include "jacobi.h"
 #include "kernels.h"
@@ -109,6 +114,7 @@ jac::GridArgs grid_args(const Geo &g)
 struct DeviceFacts {
     int cus = 256;
     size_t lds_per_block = 160 * 1024;
+    std::string arch = "gfx950";  // architecture name without feature flags
 };
 
 DeviceFacts device_facts()
@@ -125,6 +131,10 @@ DeviceFacts device_facts()
                 f.cus = prop.multiProcessorCount;
             if (prop.sharedMemPerBlock > 0)
                 f.lds_per_block = prop.sharedMemPerBlock;
+            std::string name(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof prop.gcnArchName));
+            name = name.substr(0, name.find(':'));
+            if (!name.empty())
+                f.arch = name;
         }
     });
     return f;
@@ -230,18 +240,162 @@ void plan_k(const Geo &g, int slots, TbPlan *p, int kchunk_req)
 }
 
 // ---------------------------------------------------------- tuning cache --
-// Choices made by jacobi_autotune, per (dtype, geometry, T), for the process.
-using TuneKey = std::tuple<int, int64_t, int64_t, int64_t, int64_t, int64_t, int>;
+// Choices made by jacobi_autotune (or read from a cache file), per (GPU
+// architecture, dtype, geometry, T).  A file named by JACOBI_TUNE_CACHE is
+// read at the first lookup and rewritten after every autotuning run.
+using TuneKey = std::tuple<std::string, int, int64_t, int64_t, int64_t, int64_t, int64_t, int>;
+struct TuneEntry {
+    jac_tile_t tile;
+    float ms;
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, jac_tile_t> g_tune;
+std::map<TuneKey, TuneEntry> g_tune;
+
+const char *tune_env_path()
+{
+    const char *p = getenv("JACOBI_TUNE_CACHE");
+    return p && *p ? p : nullptr;
+}
+
+// One line of a cache file: "arch dtype nx ny nz sy sz T t bx by waves kchunk ms".
+bool parse_tune_line(const char *line, TuneKey *key, TuneEntry *val, std::string *why)
+{
+    char arch[64], dt[8];
+    long long nx, ny, nz, sy, sz;
+    int T, t, bx, by, waves, kchunk, used = 0;
+    float ms;
+    if (sscanf(line, "%63s %7s %lld %lld %lld %lld %lld %d %d %d %d %d %d %f %n", arch, dt, &nx, &ny,
+               &nz, &sy, &sz, &T, &t, &bx, &by, &waves, &kchunk, &ms, &used) != 14 ||
+        line[used] != '\0') {
+        *why = "expected: arch dtype nx ny nz sy sz T t bx by waves kchunk ms";
+        return false;
+    }
+    for (const char *c = arch; *c; ++c)
+        if (!isalnum((unsigned char)*c) && *c != '_' && *c != '-' && *c != '+') {
+            *why = "bad architecture name";
+            return false;
+        }
+    const int dtype = strcmp(dt, "f64") == 0 ? JAC_F64 : strcmp(dt, "f32") == 0 ? JAC_F32 : -1;
+    if (dtype < 0) {
+        *why = "dtype must be f32 or f64";
+        return false;
+    }
+    const jac_grid_t g{nx, ny, nz, sy, sz};
+    Geo geo;
+    if (check_grid(&g, &geo) != JAC_OK || geo.sy != sy || geo.sz != sz) {
+        *why = "bad geometry";
+        return false;
+    }
+    if (T < 1 || t < 1 || t > JAC_MAX_DEPTH || t > T || kchunk < 0 || !(ms >= 0.f) ||
+        !find_shape(bx, by, waves) || waves == 0) {
+        *why = "T, t, block shape, kchunk or time out of range";
+        return false;
+    }
+    *key = TuneKey{arch, dtype, nx, ny, nz, sy, sz, T};
+    *val = TuneEntry{jac_tile_t{t, bx, by, kchunk, waves}, ms};
+    return true;
+}
+
+// Reads a cache file; all lines or none are added.  Caller holds g_tune_mu.
+int load_tune_file(const char *path, int *n_loaded)
+{
+    FILE *f = fopen(path, "r");
+    if (!f)
+        return fail(JAC_EARG, "cannot open %s", path);
+    std::vector<std::pair<TuneKey, TuneEntry>> got;
+    char line[512];
+    int lineno = 0, rc = JAC_OK;
+    while (fgets(line, sizeof line, f)) {
+        ++lineno;
+        size_t n = strlen(line);
+        if (n + 1 == sizeof line && line[n - 1] != '\n') {
+            rc = fail(JAC_EARG, "%s:%d: line too long", path, lineno);
+            break;
+        }
+        while (n && (line[n - 1] == '\n' || line[n - 1] == '\r' || line[n - 1] == ' '))
+            line[--n] = '\0';
+        const char *p = line;
+        while (*p == ' ' || *p == '\t')
+            ++p;
+        if (*p == '\0' || *p == '#')
+            continue;
+        TuneKey k;
+        TuneEntry v;
+        std::string why;
+        if (!parse_tune_line(p, &k, &v, &why)) {
+            rc = fail(JAC_EARG, "%s:%d: %s", path, lineno, why.c_str());
+            break;
+        }
+        got.emplace_back(k, v);
+    }
+    if (rc == JAC_OK && ferror(f))
+        rc = fail(JAC_EARG, "error reading %s", path);
+    fclose(f);
+    if (rc != JAC_OK)
+        return rc;
+    for (const auto &kv : got)
+        g_tune[kv.first] = kv.second;
+    if (n_loaded)
+        *n_loaded = (int)got.size();
+    return JAC_OK;
+}
+
+// Writes every remembered choice to path (via a temporary file and a rename).
+// Caller holds g_tune_mu.
+int save_tune_file(const char *path)
+{
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f)
+        return fail(JAC_EARG, "cannot write %s", tmp.c_str());
+    bool ok = fprintf(f, "# jacobi autotuning choices, format 1\n"
+                         "# arch dtype nx ny nz sy sz T t bx by waves kchunk ms\n") > 0;
+    for (const auto &kv : g_tune) {
+        const TuneKey &k = kv.first;
+        const jac_tile_t &c = kv.second.tile;
+        ok = ok && fprintf(f, "%s %s %lld %lld %lld %lld %lld %d %d %d %d %d %d %.6g\n",
+                           std::get<0>(k).c_str(), std::get<1>(k) == JAC_F64 ? "f64" : "f32",
+                           (long long)std::get<2>(k), (long long)std::get<3>(k),
+                           (long long)std::get<4>(k), (long long)std::get<5>(k),
+                           (long long)std::get<6>(k), std::get<7>(k), c.t, c.bx, c.by, c.waves,
+                           c.kchunk, (double)kv.second.ms) > 0;
+    }
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || rename(tmp.c_str(), path) != 0) {
+        remove(tmp.c_str());
+        return fail(JAC_EARG, "cannot write %s", path);
+    }
+    return JAC_OK;
+}
+
+// The JACOBI_TUNE_CACHE file, read once (a file that does not exist yet is
+// no error; one that does not parse is reported on stderr and ignored).
+void load_env_tune_once()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char *path = tune_env_path();
+        if (!path)
+            return;
+        FILE *probe = fopen(path, "r");
+        if (!probe)
+            return;
+        fclose(probe);
+        const std::string saved = g_err;
+        if (load_tune_file(path, nullptr) != JAC_OK)
+            fprintf(stderr, "libjacobi: ignoring the tuning cache: %s\n", g_err.c_str());
+        g_err = saved;
+    });
+}
 
 bool tuned(int dtype, const Geo &g, int T, jac_tile_t *out)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(TuneKey{dtype, g.nx, g.ny, g.nz, g.sy, g.sz, T});
+    load_env_tune_once();
+    auto it = g_tune.find(TuneKey{device_facts().arch, dtype, g.nx, g.ny, g.nz, g.sy, g.sz, T});
     if (it == g_tune.end())
         return false;
-    *out = it->second;
+    *out = it->second.tile;
     return true;
 }
 
@@ -1053,6 +1207,24 @@ int jacobi_fill(int dtype, const jac_grid_t *g, void *x, double value, void *str
     return e == hipSuccess ? JAC_OK : hip_fail(e, "fill launch");
 }
 
+int jacobi_grid_add(int dtype, const jac_grid_t *g, void *dst, const void *src, void *stream)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_grid(g, &geo)) ||
+        (rc = check_ptr(dst, dtype, "dst")) || (rc = check_ptr(src, dtype, "src")))
+        return rc;
+    const size_t bytes = (size_t)geo.span * elem_size(dtype);
+    if (dst != src && overlap(dst, bytes, src, bytes))
+        return fail(JAC_EARG, "dst and src overlap (only dst == src may share memory)");
+    const hipStream_t st = (hipStream_t)stream;
+    hipError_t e = dtype == JAC_F64
+                       ? jac::launch_grid_add<double>((double *)dst, (const double *)src, grid_args(geo), st)
+                       : jac::launch_grid_add<float>((float *)dst, (const float *)src, grid_args(geo), st);
+    return e == hipSuccess ? JAC_OK : hip_fail(e, "grid add launch");
+}
+
 static int batch_common(int dtype, int n, const jac_grid_t *g, const int *T, const jac_tile_t *tile,
                         jac_tile_t *tl, GridPlan **plans_out, BatchSizes *bs)
 {
@@ -1444,12 +1616,65 @@ int jacobi_autotune(int dtype, const jac_grid_t *g, void *a, void *b, int T, int
         return fail(JAC_EUNSUPPORTED, "no candidate fits this grid");
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[TuneKey{dtype, geo.nx, geo.ny, geo.nz, geo.sy, geo.sz, T}] = pick;
+        load_env_tune_once();
+        g_tune[TuneKey{device_facts().arch, dtype, geo.nx, geo.ny, geo.nz, geo.sy, geo.sz, T}] =
+            TuneEntry{pick, best};
+        if (const char *path = tune_env_path())
+            if (save_tune_file(path) != JAC_OK)
+                fprintf(stderr, "libjacobi: tuning cache not saved: %s\n", g_err.c_str());
     }
     *best_host = pick;
     if (best_ms_host)
         *best_ms_host = best;
     g_err.clear();
+    return JAC_OK;
+}
+
+int jacobi_tune_save(const char *path)
+{
+    g_err.clear();
+    if (!path || !*path)
+        return fail(JAC_EARG, "path is NULL or empty");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_env_tune_once();
+    return save_tune_file(path);
+}
+
+int jacobi_tune_load(const char *path, int *n_loaded)
+{
+    g_err.clear();
+    if (!path || !*path)
+        return fail(JAC_EARG, "path is NULL or empty");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_env_tune_once();
+    return load_tune_file(path, n_loaded);
+}
+
+int jacobi_tune_lookup(const char *arch, int dtype, const jac_grid_t *g, int T, jac_tile_t *tile_host)
+{
+    g_err.clear();
+    Geo geo;
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_grid(g, &geo)))
+        return rc;
+    if (!tile_host)
+        return fail(JAC_EARG, "tile_host is NULL");
+    const std::string a = arch ? std::string(arch) : device_facts().arch;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_env_tune_once();
+    auto it = g_tune.find(TuneKey{a, dtype, geo.nx, geo.ny, geo.nz, geo.sy, geo.sz, T});
+    if (it == g_tune.end())
+        return fail(JAC_EUNSUPPORTED, "no tuned choice for %s, this geometry and T = %d", a.c_str(), T);
+    *tile_host = it->second.tile;
+    return JAC_OK;
+}
+
+int jacobi_tune_forget(void)
+{
+    g_err.clear();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_env_tune_once();  // so that a later first lookup does not bring the file back
+    g_tune.clear();
     return JAC_OK;
 }
 

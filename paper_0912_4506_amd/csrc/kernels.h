@@ -189,6 +189,8 @@ hipError_t noalloc_scratch(double **out);
 template <typename real>
 hipError_t launch_grid_fill(real *x, real v, const GridArgs &g, hipStream_t st);
 hipError_t launch_update(double *x, const float *e32, const GridArgs &g, hipStream_t st);
+template <typename real>
+hipError_t launch_grid_add(real *dst, const real *src, const GridArgs &g, hipStream_t st);
 
 hipError_t launch_batched(int dtype, int cfg, int depth, int fixed, const BatchLaunch &L, int nblocks,
                           hipStream_t st);

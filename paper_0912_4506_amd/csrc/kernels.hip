@@ -789,6 +789,64 @@ hipError_t launch_grid_fill(real *x, real v, const GridArgs &g, hipStream_t st)
 template hipError_t launch_grid_fill<float>(float *, float, const GridArgs &, hipStream_t);
 template hipError_t launch_grid_fill<double>(double *, double, const GridArgs &, hipStream_t);
 
+// dst += src on every element (i, j, k) of a grid, shell included
+template <typename real>
+__global__ __launch_bounds__(256) void grid_add_kernel(real *__restrict__ dst,
+                                                       const real *__restrict__ src, GridArgs g)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * RES_ROWS;
+    const int64_t k0 = (int64_t)blockIdx.z * RES_KC;
+    if (i > g.nx + 1)
+        return;
+    for (int64_t k = k0; k < k0 + RES_KC && k <= g.nz + 1; ++k)
+        for (int64_t j = j0; j < j0 + RES_ROWS && j <= g.ny + 1; ++j) {
+            const int64_t c = i + j * g.sy + k * g.sz;
+            dst[c] = dst[c] + src[c];
+        }
+}
+
+// the same on a dense grid, as one contiguous run of n elements, 16 bytes a thread
+template <typename real>
+__global__ __launch_bounds__(256) void flat_add_kernel(real *__restrict__ dst,
+                                                       const real *__restrict__ src, int64_t n)
+{
+    constexpr int PER = 16 / sizeof(real);
+    const int64_t base = ((int64_t)blockIdx.x * 256 + threadIdx.x) * PER;
+    if (base + PER <= n) {
+        typedef real vec __attribute__((ext_vector_type(PER)));
+        const vec a = *reinterpret_cast<const vec *>(dst + base);
+        const vec b = *reinterpret_cast<const vec *>(src + base);
+        vec w;
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            w[q] = a[q] + b[q];
+        *reinterpret_cast<vec *>(dst + base) = w;
+    } else {
+        for (int64_t q = base; q < n; ++q)
+            dst[q] = dst[q] + src[q];
+    }
+}
+
+template <typename real>
+hipError_t launch_grid_add(real *dst, const real *src, const GridArgs &g, hipStream_t st)
+{
+    if (g.sy == g.nx + 2 && g.sz == g.sy * (g.ny + 2) && ((uintptr_t)dst % 16) == 0 &&
+        ((uintptr_t)src % 16) == 0) {
+        const int64_t n = g.sz * (g.nz + 2);
+        const int64_t per = 16 / (int64_t)sizeof(real);
+        const int64_t blocks = ((n + per - 1) / per + 255) / 256;
+        hipLaunchKernelGGL(flat_add_kernel<real>, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, n);
+        return hipGetLastError();
+    }
+    const dim3 grid((unsigned)((g.nx + 2 + 255) / 256), (unsigned)((g.ny + 2 + RES_ROWS - 1) / RES_ROWS),
+                    (unsigned)((g.nz + 2 + RES_KC - 1) / RES_KC));
+    hipLaunchKernelGGL(grid_add_kernel<real>, grid, dim3(256), 0, st, dst, src, g);
+    return hipGetLastError();
+}
+template hipError_t launch_grid_add<float>(float *, const float *, const GridArgs &, hipStream_t);
+template hipError_t launch_grid_add<double>(double *, const double *, const GridArgs &, hipStream_t);
+
 static int grid_blocks(int64_t n)
 {
     return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));

@@ -7,6 +7,7 @@ current stream of the tensor's device); every step runs in the library's
 kernels.  The wrappers only marshal arguments.
 """
 import ctypes
+import os
 
 import torch
 
@@ -141,6 +142,18 @@ def fill(x, value):
         check(_lib.load().jacobi_fill(dtype_code(x), ctypes.byref(grid_of(x)), _ptr(x),
                                       float(value), _stream(x)))
     return x
+
+
+def grid_add(dst, src):
+    """dst += src on every element of a grid, shell included (in place;
+    returns dst).  dst and src: same dtype, shape and strides."""
+    if src.dtype != dst.dtype or src.shape != dst.shape or src.stride() != dst.stride() \
+            or src.device != dst.device:
+        raise ValueError("dst and src must have the same dtype, shape, strides and device")
+    with torch.cuda.device(dst.device):
+        check(_lib.load().jacobi_grid_add(dtype_code(dst), ctypes.byref(grid_of(dst)), _ptr(dst),
+                                          _ptr(src), _stream(dst)))
+    return dst
 
 
 def residual_workspace(x):
@@ -411,6 +424,38 @@ def autotune(a, b, T, tmax=0, reps=2):
                                           int(T), int(tmax), int(reps), ctypes.byref(best),
                                           ctypes.byref(ms), _stream(a)))
     return (best.t, best.bx, best.by, best.waves), ms.value
+
+
+def tune_save(path):
+    """Write the library's tuning choices (every architecture) to a text file."""
+    check(_lib.load().jacobi_tune_save(os.fsencode(path)))
+
+
+def tune_load(path):
+    """Add the tuning choices of a file written by tune_save (or named by
+    JACOBI_TUNE_CACHE); returns how many it held."""
+    n = ctypes.c_int(0)
+    check(_lib.load().jacobi_tune_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def tune_lookup(grid, T, dtype=torch.float64, arch=None):
+    """The remembered choice (t, bx, by, kchunk, waves) for a grid (a tensor,
+    or (nx, ny, nz)) and T on `arch` (None: the current device's), or None."""
+    g = grid_of(grid) if isinstance(grid, torch.Tensor) else Grid(*grid, 0, 0)
+    code = dtype_code(grid) if isinstance(grid, torch.Tensor) else (1 if dtype == torch.float64 else 0)
+    tile = Tile()
+    rc = _lib.load().jacobi_tune_lookup(arch.encode() if arch else None, code, ctypes.byref(g),
+                                         int(T), ctypes.byref(tile))
+    if rc == _lib.JAC_EUNSUPPORTED:
+        return None
+    check(rc)
+    return tile.t, tile.bx, tile.by, tile.kchunk, tile.waves
+
+
+def tune_forget():
+    """Forget every tuning choice of this process."""
+    check(_lib.load().jacobi_tune_forget())
 
 
 def autotune_batch(grids_a, grids_b, Ts, candidates=None, mode="relaxed", reps=2):

@@ -200,3 +200,14 @@ def test_noalloc_residual_refuses_large_grids(lib):
     rc = lib.jacobi_residual_f64_noalloc(ctypes.byref(Grid(8, 8, 8, 0, 0)), P(1 << 20), P(1 << 20),
                                          P(1 << 30), None)
     assert rc == JAC_EARG and "overlap" in err(lib)
+
+
+def test_grid_add_checks(lib):
+    g = Grid(6, 6, 6, 0, 0)
+    span = 8 * 8 * 8 * 8
+    assert lib.jacobi_grid_add(1, ctypes.byref(g), A, P((1 << 20) + span - 8), None) == JAC_EARG
+    assert "overlap" in err(lib)
+    assert lib.jacobi_grid_add(1, ctypes.byref(g), A, P((1 << 20) + 4), None) == JAC_EARG
+    assert lib.jacobi_grid_add(1, ctypes.byref(g), None, B, None) == JAC_EARG and "dst" in err(lib)
+    assert lib.jacobi_grid_add(5, ctypes.byref(g), A, B, None) == JAC_EARG
+    assert lib.jacobi_grid_add(1, ctypes.byref(Grid(6, 6, 6, 7, 0)), A, B, None) == JAC_EARG

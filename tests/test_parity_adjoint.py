@@ -110,9 +110,14 @@ def test_checkpoints_gradients(jac):
     w = [dev(inputs.adjoint_weights(nx, ny, nz, seed=s)) for s in range(3)]
     L = sum((wi * lv).sum() for wi, lv in zip(w, levels))
     L.backward()
-    ref = sum(oracle.adjoint(w[m].cpu().numpy(), lv)
-              for m, lv in enumerate((4, 8, 10)))
-    assert np.max(np.abs(ut.grad.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # the backward's order: the adjoint of the last segment, then the gradient
+    # arriving at level 8 added (one rounding per element), and so on
+    wn = [wi.cpu().numpy() for wi in w]
+    horner = oracle.adjoint(oracle.adjoint(oracle.adjoint(wn[2], 2) + wn[1], 4) + wn[0], 4)
+    assert np.array_equal(ut.grad.cpu().numpy(), horner)
+    # and, by linearity, the sum of the adjoints of each checkpoint's own loss
+    ref = sum(oracle.adjoint(wn[m], lv) for m, lv in enumerate((4, 8, 10)))
+    assert np.max(np.abs(horner - ref)) <= 1e-13 * np.max(np.abs(ref))
     # forward values bitwise
     for lv, n in zip(levels, (4, 8, 10)):
         assert np.array_equal(lv.detach().cpu().numpy(), oracle.sweeps(u, n))

@@ -180,6 +180,31 @@ def test_autotune_choice_is_used_and_exact(jac):
     assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T))
 
 
+def test_autotune_choice_survives_a_cache_file(jac, tmp_path):
+    """A tuned choice, keyed by this device's architecture, written to a file,
+    forgotten and read back: the library uses it again, bitwise."""
+    nx, ny, nz, T = 70, 50, 40, 9
+    u = inputs.grid(nx, ny, nz, seed=6)
+    a = dev(u)
+    (t, bx, by, w), _ = jac.autotune(a, torch.empty_like(a), T, tmax=4, reps=1)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    assert jac.tune_lookup(a, T) == (t, bx, by, 0, w)
+    assert jac.tune_lookup(a, T, arch=arch) == (t, bx, by, 0, w)
+    path = tmp_path / "tune.txt"
+    jac.tune_save(path)
+    assert f"{arch} f64 {nx} {ny} {nz} " in path.read_text()
+    jac.tune_forget()
+    assert jac.tune_lookup(a, T) is None
+    assert jac.tune_load(path) >= 1
+    assert jac.tune_lookup(a, T) == (t, bx, by, 0, w)
+    dt = jac.default_tile(a.shape, T)
+    assert (dt[0], dt[1], dt[2], dt[4]) == (t, bx, by, w)
+    a = dev(u)
+    out = jac.tblock(a, torch.empty_like(a), T)
+    assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T))
+    jac.tune_forget()
+
+
 def test_refused_tile_leaves_buffers_untouched(jac):
     """A block the library refuses at the requested depth is refused before
     anything is enqueued: a, b (and the adjoint's lam_a) keep their contents."""
