@@ -195,6 +195,19 @@ size_t jacobi_batched_workspace(const void *plan_host);
 int jacobi_batched_run(const void *plan_host, const void *plan_dev, void *ws,
                        size_t ws_bytes, int mode, void *stream);
 
+/* Stress form of a plan, for testing the relaxed synchronisation of a
+ * batched or pipelined plan (host only, edits plan_host in place, before it
+ * is copied to the device).  The items of each pass are shuffled
+ * (pass-ordered plans only; a pipelined plan keeps its order), and about a
+ * quarter of all items get a start delay of 1..max_delay sleep rounds of
+ * about 3.4 us each (max_delay 0..64; 0 = no delays), both drawn from
+ * `seed` (splitmix64).  Every item still waits only on items of earlier
+ * passes, so the waits still end; a run of the stressed plan must give
+ * bitwise the results of the plain one.  plan_bytes: the size of the buffer
+ * at plan_host. */
+int jacobi_batched_stress(void *plan_host, size_t plan_bytes, unsigned seed,
+                          int max_delay);
+
 /* Pipelined temporal blocking of one grid: the team pipeline of Sect. 1.3 with
  * the relaxed synchronisation of Sect. 1.3 (both conditions of Eq. 3), in GPU
  * form.  T sweeps are cut into passes of tile->t sweeps (t = 0: 1 sweep per

@@ -75,6 +75,7 @@ SIGNATURES = {
     "jacobi_batched_plan": ([ctypes.c_int, ctypes.c_int, _GP, ctypes.POINTER(_P),
                              ctypes.POINTER(_P), _IP, _TP, _P, ctypes.c_size_t, _IP], ctypes.c_int),
     "jacobi_batched_workspace": ([_P], ctypes.c_size_t),
+    "jacobi_batched_stress": ([_P, ctypes.c_size_t, ctypes.c_uint, ctypes.c_int], ctypes.c_int),
     "jacobi_batched_run": ([_P, _P, _P, ctypes.c_size_t, ctypes.c_int, _P], ctypes.c_int),
     "jacobi_pipelined_plan_bytes": ([ctypes.c_int, _GP, ctypes.c_int, _TP], ctypes.c_size_t),
     "jacobi_pipelined_plan": ([ctypes.c_int, _GP, _P, _P, ctypes.c_int, ctypes.c_int,

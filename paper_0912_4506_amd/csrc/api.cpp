@@ -1466,6 +1466,47 @@ static int read_header(const void *plan_host, jac::BatchHeader *h)
     return JAC_OK;
 }
 
+// splitmix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): the stress permutation and delays
+static uint64_t splitmix64(uint64_t *state)
+{
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+int jacobi_batched_stress(void *plan_host, size_t plan_bytes, unsigned seed, int max_delay)
+{
+    g_err.clear();
+    jac::BatchHeader h;
+    int rc;
+    if ((rc = read_header(plan_host, &h)))
+        return rc;
+    if ((size_t)h.total_bytes > plan_bytes)
+        return fail(JAC_EARG, "plan_bytes = %zu is below the image size %lld", plan_bytes,
+                    (long long)h.total_bytes);
+    if (max_delay < 0 || max_delay > 64)
+        return fail(JAC_EARG, "max_delay = %d outside 0..64", max_delay);
+    unsigned char *img = (unsigned char *)plan_host;
+    jac::BatchItem *items = (jac::BatchItem *)(img + h.items_off);
+    const int *pass_start = (const int *)(img + h.pass_off);
+    uint64_t state = seed;
+    if (h.order == 0)  // pass-ordered plans: every item waits on earlier passes only
+        for (int pass = 0; pass < h.maxpasses; ++pass) {
+            const int lo = pass_start[pass], hi = pass_start[pass + 1];
+            for (int i = hi - 1; i > lo; --i) {  // Fisher-Yates over [lo, hi)
+                const int j = lo + (int)(splitmix64(&state) % (uint64_t)(i - lo + 1));
+                std::swap(items[i], items[j]);
+            }
+        }
+    for (int i = 0; i < h.nitems; ++i) {
+        const uint64_t r = splitmix64(&state);
+        items[i].delay = (max_delay > 0 && r % 4 == 0) ? 1 + (int)((r >> 2) % (uint64_t)max_delay) : 0;
+    }
+    return JAC_OK;
+}
+
 size_t jacobi_batched_workspace(const void *plan_host)
 {
     g_err.clear();

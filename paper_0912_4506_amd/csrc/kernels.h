@@ -118,9 +118,10 @@ struct BatchGrid {
 
 // One block of one pass of one grid.  Items are ordered pass by pass, or in
 // pipeline wavefronts; in either order every block an item waits on comes
-// earlier.
+// earlier.  delay: sleep rounds (s_sleep 127, about 3.4 us each) before the
+// item starts; 0 except in stress runs of the relaxed synchronisation.
 struct BatchItem {
-    int grid, pass, tile, pad;
+    int grid, pass, tile, delay;
 };
 
 // Persistent (relaxed) mode: blocks pop items in order and wait for the

@@ -642,6 +642,10 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(BatchLaunch L)
         if (it >= L.end)
             break;
         const BatchItem m = L.items[it];
+        // stress runs only: hold the item back before it reads or writes
+        // anything (the waits of the items that need it absorb the delay)
+        for (int s = 0; s < m.delay; ++s)
+            __builtin_amdgcn_s_sleep(127);
         const BatchGrid G = L.grids[m.grid];
         const int ti = m.tile % G.nti;
         const int tj = (m.tile / G.nti) % G.ntj;

@@ -273,6 +273,24 @@ class BatchPlan:
                                                  _stream(self.plan_dev)))
         return self
 
+    def stress(self, seed, max_delay=8):
+        """Shuffle the items of each pass and delay some of them
+        (jacobi_batched_stress), then refresh the device copy: a test of the
+        relaxed synchronisation, whose results must not change."""
+        check(_lib.load().jacobi_batched_stress(self._host, len(self._host), int(seed),
+                                                int(max_delay)))
+        self.plan_dev.copy_(torch.frombuffer(bytearray(self._host), dtype=torch.uint8))
+        return self
+
+    def items(self):
+        """The plan's work items (grid, pass, block, delay) in queue order,
+        read back from the host image (layout in csrc/kernels.h)."""
+        import struct
+        raw = bytes(self._host)
+        hdr = struct.unpack_from("<I9i5q", raw, 0)
+        nitems, items_off = hdr[3], hdr[11]
+        return [struct.unpack_from("<4i", raw, items_off + 16 * i) for i in range(nitems)]
+
     def results(self):
         return [b if o else a for a, b, o in zip(self.a, self.b, self.out_idx)]
 

@@ -218,3 +218,24 @@ def test_batch_64_grids_graph_replays_bench_pick(jac, batch64):
         assert not plan.wait_error()
         for m, (ref, out) in enumerate(zip(refs, plan.results())):
             assert torch.equal(out, ref), (rep, m)
+
+
+@pytest.mark.parametrize("mode", ["relaxed", "lockstep"])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_batched_stress_bitwise(jac, mode, seed):
+    """Race test of the per-block counters: the items of each pass shuffled
+    and about a quarter of them held back by up to 8 sleep rounds before they
+    start (jacobi_batched_stress), so consumers often reach a counter before
+    its producer has started.  Results are bitwise those of the oracle and
+    no wait gives up."""
+    Ts = [20, 17, 23, 9, 4, 31, 12]
+    us, a, b = make_batch(SHAPES, seed=seed)
+    plan = jac.BatchPlan(a, b, Ts, t=3, bx=64, by=48, kchunk=16).stress(seed, 8)
+    items = plan.items()
+    assert any(d for *_, d in items)
+    assert [p for _, p, _, _ in items] == sorted(p for _, p, _, _ in items)
+    plan.run(mode)
+    torch.cuda.synchronize()
+    assert not plan.wait_error()
+    for m, (u, T, out) in enumerate(zip(us, Ts, plan.results())):
+        assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T)), (m, mode, seed)

@@ -83,3 +83,20 @@ def test_pipelined_relaxed_sync_bitwise(jac, shape, T, team, t, kchunk, sync):
         torch.cuda.synchronize()
         assert not plan.wait_error(), (sync, rep)
         assert np.array_equal(plan.results()[0].cpu().numpy(), ref), (sync, rep)
+
+
+@pytest.mark.parametrize("sync,seed", [((1, 1, 0), 5), ((1, 2, 0), 6), ((2, 3, 1), 7)])
+def test_pipelined_stress_bitwise(jac, sync, seed):
+    """The pipelined order with about a quarter of the items held back by up
+    to 16 sleep rounds before they start: the Eq. 3 waits absorb the delays
+    and the result stays bitwise the oracle's."""
+    dl, du, dt = sync
+    shape, T = (130, 70, 120), 12
+    u = inputs.grid(*shape, seed=seed)
+    a = dev(u)
+    b = torch.full_like(a, float("nan"))
+    plan = jac.PipelinePlan(a, b, T, team=4, t=1, kchunk=8, dl=dl, du=du, dt=dt).stress(seed, 16)
+    plan.run("relaxed")
+    torch.cuda.synchronize()
+    assert not plan.wait_error(), sync
+    assert np.array_equal(plan.results()[0].cpu().numpy(), oracle.sweeps(u, T)), sync

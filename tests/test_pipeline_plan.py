@@ -200,3 +200,79 @@ def test_relaxed_sync_argument_checks(lib):
                                    out) == 0
     p = parse(bb)
     assert (p["gteam"], p["du"], p["dt"]) == (0, 0, 0)
+
+
+def batch_buf(lib, shapes, Ts, t=2, bx=64, by=72, waves=12, kchunk=16):
+    n = len(shapes)
+    G = (Grid * n)(*[Grid(*s, 0, 0) for s in shapes])
+    T = (ctypes.c_int * n)(*Ts)
+    tile = Tile(t, bx, by, kchunk, waves)
+    nb = lib.jacobi_batched_plan_bytes(1, n, G, T, ctypes.byref(tile))
+    buf = (ctypes.c_ubyte * nb)()
+    A = (ctypes.c_void_p * n)(*[(2 * m + 1) << 32 for m in range(n)])
+    B = (ctypes.c_void_p * n)(*[(2 * m + 2) << 32 for m in range(n)])
+    assert lib.jacobi_batched_plan(1, n, G, A, B, T, ctypes.byref(tile), buf, nb,
+                                   (ctypes.c_int * n)()) == 0, lib.jacobi_last_error()
+    return buf
+
+
+def all_items(buf):
+    raw = bytes(buf)
+    h = HDR.unpack_from(raw, 0)
+    return [struct.unpack_from("<4i", raw, h[11] + 16 * n) for n in range(h[3])]
+
+
+def test_stress_shuffles_within_passes_and_delays(lib):
+    """jacobi_batched_stress: each pass keeps its item set and its place in
+    the queue (so every wait still points to an earlier item), the order
+    inside passes changes, about a quarter of the items get a delay in
+    1..max_delay, and the same seed gives the same image."""
+    buf = batch_buf(lib, [(130, 70, 64), (40, 30, 20), (90, 90, 33)], [7, 4, 6])
+    before = all_items(buf)
+    assert all(d == 0 for *_, d in before)
+    keep = bytes(buf)
+    assert lib.jacobi_batched_stress(buf, len(buf), 12345, 8) == 0
+    after = all_items(buf)
+    assert [x[:3] for x in after] != [x[:3] for x in before]
+    passes_before = [x[1] for x in before]
+    assert [x[1] for x in after] == passes_before          # pass boundaries unchanged
+    for pas in set(passes_before):
+        assert sorted(x[:3] for x in after if x[1] == pas) == \
+            sorted(x[:3] for x in before if x[1] == pas)
+    delays = [x[3] for x in after]
+    assert all(0 <= d <= 8 for d in delays)
+    frac = sum(d > 0 for d in delays) / len(delays)
+    assert 0.15 < frac < 0.35, frac
+    assert set(d for d in delays if d) == set(range(1, 9))
+    # the same seed on the original image gives the same stressed image
+    again = (ctypes.c_ubyte * len(buf)).from_buffer_copy(keep)
+    assert lib.jacobi_batched_stress(again, len(again), 12345, 8) == 0
+    assert bytes(again) == bytes(buf)
+    # the header, grids and pass table are untouched
+    h = HDR.unpack_from(keep, 0)
+    assert bytes(buf)[:h[11]] == keep[:h[11]] and bytes(buf)[h[12]:] == keep[h[12]:]
+    # max_delay 0: shuffle only
+    only = (ctypes.c_ubyte * len(buf)).from_buffer_copy(keep)
+    assert lib.jacobi_batched_stress(only, len(only), 7, 0) == 0
+    assert all(x[3] == 0 for x in all_items(only))
+
+
+def test_stress_keeps_the_pipelined_order(lib):
+    p, _, buf = plan(lib, (130, 70, 64), 20, 7, 1, 4, sync=(1, 2, 1))
+    before = all_items(buf)
+    assert lib.jacobi_batched_stress(buf, len(buf), 99, 16) == 0
+    after = all_items(buf)
+    assert [x[:3] for x in after] == [x[:3] for x in before]
+    assert any(x[3] for x in after) and max(x[3] for x in after) <= 16
+    check_order(parse(buf))
+
+
+def test_stress_argument_checks(lib):
+    buf = batch_buf(lib, [(40, 30, 20)], [4])
+    assert lib.jacobi_batched_stress(buf, len(buf), 1, 65) == JAC_EARG
+    assert lib.jacobi_batched_stress(buf, len(buf), 1, -1) == JAC_EARG
+    assert lib.jacobi_batched_stress(buf, len(buf) - 16, 1, 4) == JAC_EARG
+    assert "plan_bytes" in lib.jacobi_last_error().decode()
+    assert lib.jacobi_batched_stress(None, 0, 1, 4) == JAC_EARG
+    junk = (ctypes.c_ubyte * 256)()
+    assert lib.jacobi_batched_stress(junk, 256, 1, 4) == JAC_EARG
