@@ -9,7 +9,8 @@ it was measured with, so the benchmark reports those figures only while the
 kernel is unchanged.
 
 Build one from the CSV directories of four rocprofv3 runs (kernel trace, then
-FETCH_SIZE, WRITE_SIZE and the SQ counters, each in a run of its own):
+FETCH_SIZE, WRITE_SIZE and one or more sets of SQ counters, each in a run of
+its own):
 
     python -m paper_0912_4506_amd.profiling --kernel 'tblock_kernel<double, 4, 1, 6, 12, 0>' \\
         --trace DIR --fetch DIR --write DIR --sq DIR --title '...' --command '...' \\
@@ -92,7 +93,8 @@ def median(v):
 
 def summarize(kernel, trace=None, fetch=None, write=None, sq=None, copy="jac::copy_kernel",
               copy_bytes=2 << 30):
-    """Figures of `kernel` (a fragment of its name) from the run directories."""
+    """Figures of `kernel` (a fragment of its name) from the run directories
+    (sq: one directory of SQ/GRBM counter runs, or a list of them)."""
     fig = {"kernel_source_sha": kernel_source_hash()}
     if trace:
         times = kernel_times(trace)
@@ -115,8 +117,8 @@ def summarize(kernel, trace=None, fetch=None, write=None, sq=None, copy="jac::co
         fig[f"{label}_gb_per_launch"] = round(kib * 1024.0 * scale / 1e9, 4)
     if "fetch_gb_per_launch" in fig and "write_gb_per_launch" in fig:
         fig["traffic_gb_per_launch"] = round(fig["fetch_gb_per_launch"] + fig["write_gb_per_launch"], 4)
-    if sq:
-        c = counters(sq)
+    for d in ([sq] if isinstance(sq, str) else (sq or [])):
+        c = counters(d)
         name = _match(c, kernel)
         for counter, vals in sorted(c[name].items()):
             fig[counter.lower() + "_per_launch"] = round(median(vals))
@@ -171,7 +173,7 @@ def main():
     ap.add_argument("--trace")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
-    ap.add_argument("--sq")
+    ap.add_argument("--sq", action="append", help="SQ counter run (repeatable)")
     ap.add_argument("--title", required=True)
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--notes", default="")
