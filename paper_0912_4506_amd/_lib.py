@@ -87,6 +87,8 @@ SIGNATURES = {
     "jacobi_tile_menu": ([ctypes.c_int, _IP, ctypes.c_int], ctypes.c_int),
     "lbm_d3q19_steps": ([ctypes.c_int, ctypes.POINTER(LbmGrid), _P, _P, ctypes.c_double,
                          ctypes.c_int, _P, _IP], ctypes.c_int),
+    "lbm_d3q19_blocked": ([ctypes.c_int, ctypes.POINTER(LbmGrid), _P, _P, ctypes.c_double,
+                           ctypes.c_int, ctypes.c_int, _P, _IP], ctypes.c_int),
     "jacobi_autotune": ([ctypes.c_int, _GP, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _TP,
                          ctypes.POINTER(ctypes.c_float), _P], ctypes.c_int),
     "jacobi_default_tile": ([ctypes.c_int, _GP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _TP],

@@ -208,6 +208,14 @@ struct LbmArgs {
 };
 template <typename real>
 hipError_t launch_lbm_d3q19(const real *f, real *out, const LbmArgs &p, hipStream_t st);
+// Two steps in one pass (temporal blocking at depth 2): z chunks of `kchunk`
+// output planes per workgroup.
+template <typename real>
+hipError_t launch_lbm_d3q19_x2(const real *f, real *out, const LbmArgs &p, int kchunk,
+                               hipStream_t st);
+// Shape of the depth-2 pass: the workgroup's level-1 region (x by y cells,
+// one per thread) and the output tile inside it (one cell less per side).
+constexpr int kLbm2X = 32, kLbm2Y = 8;
 
 // Per-lane scratch (register spill) bytes of a tblock instance, -1 if none.
 int tblock_scratch(int dtype, int cfg, int depth, int mode);

@@ -504,10 +504,12 @@ def autotune_batch(grids_a, grids_b, Ts, candidates=None, mode="relaxed", reps=2
     return best, best_ms
 
 
-def lbm_d3q19(f, f_tmp, omega, T):
+def lbm_d3q19(f, f_tmp, omega, T, blocked=False, kchunk=0):
     """T D3Q19 lattice Boltzmann steps (BGK, periodic box) on populations f of
     shape (19, nz, ny, nx) (contiguous, float32 or float64); f_tmp is a second
-    buffer like f.  Returns the tensor (f or f_tmp) holding step T."""
+    buffer like f.  blocked: two steps per pass over memory
+    (lbm_d3q19_blocked; kchunk z planes per workgroup, 0 = library choice),
+    bitwise the same results.  Returns the tensor (f or f_tmp) holding step T."""
     if f.shape != f_tmp.shape or f.dtype != f_tmp.dtype or f.device != f_tmp.device:
         raise ValueError("f and f_tmp must share shape, dtype and device")
     if f.dim() != 4 or f.shape[0] != 19 or not (f.is_contiguous() and f_tmp.is_contiguous()):
@@ -515,7 +517,13 @@ def lbm_d3q19(f, f_tmp, omega, T):
     _, nz, ny, nx = f.shape
     out = ctypes.c_int(0)
     with torch.cuda.device(f.device):
-        check(_lib.load().lbm_d3q19_steps(dtype_code(f), ctypes.byref(_lib.LbmGrid(nx, ny, nz)),
-                                          _ptr(f), _ptr(f_tmp), float(omega), int(T), _stream(f),
-                                          ctypes.byref(out)))
+        lib = _lib.load()
+        if blocked:
+            check(lib.lbm_d3q19_blocked(dtype_code(f), ctypes.byref(_lib.LbmGrid(nx, ny, nz)),
+                                        _ptr(f), _ptr(f_tmp), float(omega), int(T), int(kchunk),
+                                        _stream(f), ctypes.byref(out)))
+        else:
+            check(lib.lbm_d3q19_steps(dtype_code(f), ctypes.byref(_lib.LbmGrid(nx, ny, nz)),
+                                      _ptr(f), _ptr(f_tmp), float(omega), int(T), _stream(f),
+                                      ctypes.byref(out)))
     return f_tmp if out.value else f

@@ -191,6 +191,17 @@ def test_lbm_argument_checks(lib):
     OUT.value = 5
     assert call(T=0) == 0 and OUT.value == 0
 
+    def blocked(grid=g, T=2, kchunk=0, ft=P((1 << 20) + n)):
+        return lib.lbm_d3q19_blocked(1, ctypes.byref(grid), A, ft, 1.0, T, kchunk, None,
+                                     ctypes.byref(OUT))
+
+    assert blocked(kchunk=-1) == JAC_EARG and "kchunk" in err(lib)
+    assert blocked(kchunk=70000) == JAC_EARG
+    assert blocked(grid=LbmGrid(8, 400000, 2), ft=P(1 << 40)) == JAC_EARG and "ny/6" in err(lib)
+    assert blocked(ft=P((1 << 20) + n - 8)) == JAC_EARG and "overlap" in err(lib)
+    OUT.value = 5
+    assert blocked(T=0) == 0 and OUT.value == 0
+
 
 def test_noalloc_residual_refuses_large_grids(lib):
     """More partial sums than the fixed array holds: refused before any HIP call."""

@@ -90,6 +90,8 @@ def calls(lib):
                                                     ctypes.byref(OUT)),
         "lbm": lambda: lib.lbm_d3q19_steps(1, ctypes.byref(LbmGrid(16, 8, 8)), addr(0), addr(1),
                                            1.2, 2, None, ctypes.byref(OUT)),
+        "lbm_blocked": lambda: lib.lbm_d3q19_blocked(1, ctypes.byref(LbmGrid(16, 8, 8)), addr(0),
+                                                     addr(1), 1.2, 2, 0, None, ctypes.byref(OUT)),
         "autotune": lambda: lib.jacobi_autotune(1, g, addr(0), addr(1), 4, 2, 1, ctypes.byref(best),
                                                 ctypes.byref(ms), None),
     }
@@ -100,7 +102,7 @@ def test_every_enqueuing_entry_point_reports_the_hip_error():
     table = calls(lib)
     assert set(table) >= {"plain", "tblock", "adjoint", "residual", "residual_noalloc", "update",
                           "update_residual", "fill", "grid_add", "copy", "batched_relaxed",
-                          "pipelined", "compressed", "lbm", "autotune"}
+                          "pipelined", "compressed", "lbm", "lbm_blocked", "autotune"}
     for name, call in table.items():
         rc = call()
         msg = lib.jacobi_last_error().decode()
