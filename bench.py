@@ -649,7 +649,7 @@ def bench_lbm(args):
             "data": "synthetic: populations (1 + 0.1 U[0,1)) / 19, numpy default_rng(0)",
             "config": {"workload": f"D3Q19 BGK {n}^3, omega 1.7, {T} steps per step",
                        "method": {"plain": "one step per pass, 64x4 blocks",
-                                  "t2": "two steps per pass, 32x8 regions, 30x6 output tiles"}[best]},
+                                  "t2": "two steps per pass, 32x8 regions, 30x6 output tiles (FP32: 32x16)"}[best]},
             "roofline": {"bound": "hbm", "achieved": f64["achieved_gbs"], "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": f64["frac"], "traffic": None,
                          "algorithmic_bytes_per_lup": f64["bytes_per_lup"]},

@@ -59,14 +59,16 @@ int lbm_d3q19_steps(int dtype, const lbm_grid_t *g, void *f, void *f_tmp, double
  * steps per pass over memory): each pass reads the populations once and
  * writes them once for two steps, keeping the intermediate step's
  * populations on chip.  A workgroup computes the intermediate step on a
- * region of 32 x 8 cells (x, y) and the second step on the 30 x 6 cells
- * inside it, streaming z chunks of kchunk planes (0 = library choice: 12
- * in FP64, 4 in FP32, or nz if smaller; 1..65535).  An odd T ends with one plain step.  Every
+ * region of 32 x 8 cells (x, y; 32 x 16 in FP32) and the second step on the
+ * cells one inside it (30 x 6, or 30 x 14), streaming z chunks of kchunk
+ * planes (0 = library choice: 12 in FP64, 4 in FP32, or nz if smaller;
+ * 1..65535).  An odd T ends with one plain step.  Every
  * cell runs the same arithmetic as lbm_d3q19_steps, so the results are
  * bitwise those of lbm_d3q19_steps (and of the plain sequential scheme
  * above).  Buffers alternate once per pass: *out_idx = (number of passes
  * plus the plain step) mod 2 names the one holding step T.  Other arguments
- * and errors as for lbm_d3q19_steps; ceil(ny/6) must not exceed 65535. */
+ * and errors as for lbm_d3q19_steps; ceil(ny/6) (FP32: ceil(ny/14)) must not
+ * exceed 65535. */
 int lbm_d3q19_blocked(int dtype, const lbm_grid_t *g, void *f, void *f_tmp, double omega, int T,
                       int kchunk, void *stream, int *out_idx);
 

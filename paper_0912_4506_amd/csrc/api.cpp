@@ -1811,11 +1811,12 @@ int lbm_d3q19_blocked(int dtype, const lbm_grid_t *g, void *f, void *f_tmp, doub
     // against 17.2 at 64; FP32 37.6 at 4 against 29.8)
     const int def_kc = dtype == JAC_F64 ? 12 : 4;
     const int kc = (int)std::min<int64_t>(kchunk ? kchunk : def_kc, g->nz);
-    const int64_t gx = (g->nx + jac::kLbm2X - 3) / (jac::kLbm2X - 2);
-    const int64_t gy = (g->ny + jac::kLbm2Y - 3) / (jac::kLbm2Y - 2);
+    const int rx = jac::lbm2_region_x(elem_size(dtype)), ry = jac::lbm2_region_y(elem_size(dtype));
+    const int64_t gx = (g->nx + rx - 3) / (rx - 2);
+    const int64_t gy = (g->ny + ry - 3) / (ry - 2);
     const int64_t gz = (g->nz + kc - 1) / kc;
     if (gy > 65535 || (long double)gx * gy * gz > (long double)INT_MAX / 2)
-        return fail(JAC_EARG, "box too large for the two-step pass (ceil(ny/6) <= 65535)");
+        return fail(JAC_EARG, "box too large for the two-step pass (ceil(ny/%d) <= 65535)", ry - 2);
     *out_idx = 0;
     const int64_t n = g->nx * g->ny * g->nz;
     jac::LbmArgs p{(int)g->nx, (int)g->ny, (int)g->nz, n, omega};

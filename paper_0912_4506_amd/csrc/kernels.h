@@ -214,8 +214,11 @@ template <typename real>
 hipError_t launch_lbm_d3q19_x2(const real *f, real *out, const LbmArgs &p, int kchunk,
                                hipStream_t st);
 // Shape of the depth-2 pass: the workgroup's level-1 region (x by y cells,
-// one per thread) and the output tile inside it (one cell less per side).
-constexpr int kLbm2X = 32, kLbm2Y = 8;
+// one per thread) and the output tile inside it (one cell less per side);
+// measured at 256^3: 32 x 8 in FP64 (two workgroups per CU fit the LDS),
+// 32 x 16 in FP32.
+constexpr int lbm2_region_x(size_t) { return 32; }
+constexpr int lbm2_region_y(size_t elem) { return elem == 8 ? 8 : 16; }
 
 // Per-lane scratch (register spill) bytes of a tblock instance, -1 if none.
 int tblock_scratch(int dtype, int cfg, int depth, int mode);

@@ -121,9 +121,9 @@ __global__ __launch_bounds__(kLbmX * kLbmY) void lbm_d3q19_kernel(const real *__
 
 // ---------------------------------------------------------- depth 2 pass --
 // Two time steps per pass over memory (temporal blocking, Sect. 1.1, applied
-// to the D3Q19 stream-collide step).  A workgroup of 256 threads owns a
-// level-1 region of kLbm2X x kLbm2Y cells (one per thread) and the output
-// tile one cell inside it, and streams a chunk of z planes.  At stream step s
+// to the D3Q19 stream-collide step).  A workgroup owns a level-1 region of
+// X x Y cells (one per thread; Lbm2Shape) and the output tile one cell
+// inside it, and streams a chunk of z planes.  At stream step s
 // it computes level 1 (step t+1) of plane zs = z0 - 1 + s on the whole
 // region, pulling level 0 straight from memory, then level 2 (step t+2) of
 // plane zs - 1 on the tile, pulling level 1 from LDS.  Level 2 of plane z
@@ -134,7 +134,6 @@ __global__ __launch_bounds__(kLbmX * kLbmY) void lbm_d3q19_kernel(const real *__
 // level-0 pulls of the next step are issued before the level-2 work of this
 // one.  Algorithmic traffic: one read and one write of 19 values per cell per
 // two steps.
-constexpr int kLbm2Cells = kLbm2X * kLbm2Y;
 // the populations by z velocity: group 0 (c_z = -1), 1 (c_z = 0), 2 (c_z = +1)
 constexpr int kGroup[kQ] = {1, 1, 1, 1, 1, 2, 0, 1, 1, 1, 1, 2, 0, 0, 2, 2, 0, 0, 2};
 constexpr int kGroupIdx[kQ] = {0, 1, 2, 3, 4, 0, 0, 5, 6, 7, 8, 1, 1, 2, 2, 3, 3, 4, 4};
@@ -144,16 +143,19 @@ constexpr int kGroupSlots[3] = {1, 2, 3};
 constexpr int kGroupBase[3] = {0, 5, 5 + 2 * 9};
 constexpr int kLbm2Planes = 5 + 2 * 9 + 3 * 5;  // 38
 
-__host__ __device__ constexpr size_t lbm2_lds_bytes(size_t elem)
-{
-    return (size_t)kLbm2Planes * kLbm2Cells * elem;
-}
+template <typename real>
+struct Lbm2Shape {
+    static constexpr int X = lbm2_region_x(sizeof(real)), Y = lbm2_region_y(sizeof(real));
+    static constexpr int Cells = X * Y;
+    static constexpr size_t lds = (size_t)kLbm2Planes * Cells * sizeof(real);
+};
 
 template <typename real>
-__global__ __launch_bounds__(kLbm2Cells) void lbm_d3q19_x2_kernel(const real *__restrict__ f,
-                                                                 real *__restrict__ out,
-                                                                 LbmArgs p, int kchunk)
+__global__ __launch_bounds__(Lbm2Shape<real>::Cells) void lbm_d3q19_x2_kernel(
+    const real *__restrict__ f, real *__restrict__ out, LbmArgs p, int kchunk)
 {
+    constexpr int kLbm2X = Lbm2Shape<real>::X, kLbm2Y = Lbm2Shape<real>::Y;
+    constexpr int kLbm2Cells = Lbm2Shape<real>::Cells;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     real *lds = reinterpret_cast<real *>(smem_raw);
     int tx, ty, tz;
@@ -251,7 +253,8 @@ template hipError_t launch_lbm_d3q19<double>(const double *, double *, const Lbm
 template <typename real>
 hipError_t launch_lbm_d3q19_x2(const real *f, real *out, const LbmArgs &p, int kchunk, hipStream_t st)
 {
-    const size_t lds = lbm2_lds_bytes(sizeof(real));
+    constexpr int kLbm2X = Lbm2Shape<real>::X, kLbm2Y = Lbm2Shape<real>::Y;
+    const size_t lds = Lbm2Shape<real>::lds;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)lbm_d3q19_x2_kernel<real>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -261,7 +264,8 @@ hipError_t launch_lbm_d3q19_x2(const real *f, real *out, const LbmArgs &p, int k
     const dim3 grid((unsigned)((p.nx + kLbm2X - 3) / (kLbm2X - 2)),
                     (unsigned)((p.ny + kLbm2Y - 3) / (kLbm2Y - 2)),
                     (unsigned)((p.nz + kchunk - 1) / kchunk));
-    hipLaunchKernelGGL(lbm_d3q19_x2_kernel<real>, grid, dim3(kLbm2Cells), lds, st, f, out, p, kchunk);
+    hipLaunchKernelGGL(lbm_d3q19_x2_kernel<real>, grid, dim3(Lbm2Shape<real>::Cells), lds, st, f, out,
+                       p, kchunk);
     return hipGetLastError();
 }
 

@@ -83,16 +83,19 @@ def test_lbm_blocked_fp64_bitwise(jac, shape, omega, T, kchunk):
     assert np.array_equal(run_blocked(jac, f, omega, T, kchunk=kchunk), ref)
 
 
-def test_lbm_blocked_fp32_equals_plain(jac):
-    """FP32: every cell runs the plain kernel's instruction sequence, so the
-    blocked passes equal the plain steps bitwise (and the oracle within the
-    FP32 bound)."""
-    f = inputs.lbm_populations(70, 20, 9, seed=5).astype(np.float32)
-    got = run_blocked(jac, f, 1.3, 8, torch.float32)
-    plain = run(jac, f, 1.3, 8, torch.float32)
+@pytest.mark.parametrize("shape,T,kchunk", [((70, 20, 9), 8, 0), ((1, 1, 1), 3, 0),
+                                            ((30, 14, 5), 4, 0), ((31, 15, 9), 5, 3),
+                                            ((65, 33, 17), 6, 0), ((7, 40, 6), 2, 1)])
+def test_lbm_blocked_fp32_equals_plain(jac, shape, T, kchunk):
+    """FP32 (32 x 16 regions, 30 x 14 output tiles): every cell runs the plain
+    kernel's instruction sequence, so the blocked passes equal the plain
+    steps bitwise (and the oracle within the FP32 bound)."""
+    f = inputs.lbm_populations(*shape, seed=5 + T).astype(np.float32)
+    got = run_blocked(jac, f, 1.3, T, torch.float32, kchunk=kchunk)
+    plain = run(jac, f, 1.3, T, torch.float32)
     assert np.array_equal(got, plain)
-    ref = oracle.lbm_d3q19(f.astype(np.float64), 1.3, 8)
-    assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
+    ref = oracle.lbm_d3q19(f.astype(np.float64), 1.3, T)
+    assert np.max(np.abs(got - ref)) <= 2e-6 * T * np.max(np.abs(ref))
 
 
 def test_lbm_blocked_bench_size_bitwise(jac):
