@@ -1456,6 +1456,10 @@ int jacobi_pipelined_plan(int dtype, const jac_grid_t *g, void *a, void *b, int 
     return build_plan(dtype, 1, g, aa, bb, &T, &req, plan_host, plan_bytes, out_idx_host, team, sy);
 }
 
+// The header of a plan image, checked for the layout the builder writes: the
+// grid records, the items and the pass table lie inside the image, and every
+// pass range lies inside the item list (a damaged image is refused before
+// anything reads past it).
 static int read_header(const void *plan_host, jac::BatchHeader *h)
 {
     if (!plan_host)
@@ -1463,6 +1467,22 @@ static int read_header(const void *plan_host, jac::BatchHeader *h)
     memcpy(h, plan_host, sizeof *h);
     if (h->magic != jac::BATCH_MAGIC || (h->dtype != JAC_F32 && h->dtype != JAC_F64) || h->n < 1)
         return fail(JAC_EARG, "plan_host is not a batch plan");
+    const int64_t total = h->total_bytes;
+    const bool layout_ok =
+        h->nitems >= 0 && h->ntiles >= 0 && h->maxpasses >= 0 && h->n <= 65535 &&
+        h->grids_off >= (int64_t)sizeof(jac::BatchHeader) &&
+        h->grids_off + (int64_t)h->n * (int64_t)sizeof(jac::BatchGrid) <= h->items_off &&
+        h->items_off + (int64_t)h->nitems * (int64_t)sizeof(jac::BatchItem) <= h->pass_off &&
+        h->pass_off + ((int64_t)h->maxpasses + 1) * (int64_t)sizeof(int) <= total;
+    if (!layout_ok)
+        return fail(JAC_EARG, "plan_host is not a batch plan (damaged layout)");
+    const int *pass_start = (const int *)((const unsigned char *)plan_host + h->pass_off);
+    if (pass_start[h->maxpasses] != h->nitems)
+        return fail(JAC_EARG, "plan_host is not a batch plan (damaged pass table)");
+    if (h->order == 0)
+        for (int p = 0; p < h->maxpasses; ++p)
+            if (pass_start[p] < 0 || pass_start[p] > pass_start[p + 1])
+                return fail(JAC_EARG, "plan_host is not a batch plan (damaged pass table)");
     return JAC_OK;
 }
 

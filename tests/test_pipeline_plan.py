@@ -276,3 +276,33 @@ def test_stress_argument_checks(lib):
     assert lib.jacobi_batched_stress(None, 0, 1, 4) == JAC_EARG
     junk = (ctypes.c_ubyte * 256)()
     assert lib.jacobi_batched_stress(junk, 256, 1, 4) == JAC_EARG
+
+
+def test_damaged_plan_images_are_refused(lib):
+    """An image whose offsets or pass table do not match the layout the plan
+    builder writes is refused before anything reads past it."""
+    buf = batch_buf(lib, [(40, 30, 20), (33, 17, 9)], [6, 4])
+    good = bytes(buf)
+    assert lib.jacobi_batched_workspace(buf) > 0
+    h = list(HDR.unpack_from(good, 0))
+
+    def damaged(field, value=None, pass_last=None):
+        img = (ctypes.c_ubyte * len(good)).from_buffer_copy(good)
+        if field is not None:
+            hh = list(h)
+            hh[field] = value
+            HDR.pack_into(img, 0, *hh)
+        if pass_last is not None:
+            struct.pack_into("<i", img, h[12] + 4 * h[7], pass_last)
+        return img
+
+    for img in (damaged(11, h[12] + 16),            # items past the pass table
+                damaged(3, h[3] + 1000),             # more items than the image holds
+                damaged(12, h[13]),                  # pass table past the end
+                damaged(7, h[7] + 50),               # more passes than the table holds
+                damaged(None, pass_last=h[3] - 1)):  # pass table does not end at nitems
+        assert lib.jacobi_batched_workspace(img) == 0
+        assert "not a batch plan" in lib.jacobi_last_error().decode()
+        assert lib.jacobi_batched_stress(img, len(img), 1, 4) == JAC_EARG
+        assert lib.jacobi_batched_run(img, ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 34),
+                                      1 << 20, 0, None) == JAC_EARG
