@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define JACOBI_ABI_VERSION 2
+#define JACOBI_ABI_VERSION 3
 
 /* Grid geometry.  nx, ny, nz >= 1 are the interior extents.  sy and sz are the
  * element strides of j and k; 0 selects the dense strides sy = nx+2 and
@@ -104,7 +104,9 @@ enum {
     JAC_EUNSUPPORTED = -4  /* valid request the library has no kernel for */
 };
 
-/* Library version (JACOBI_ABI_VERSION of the build). */
+/* Library version (JACOBI_ABI_VERSION of the build).  3: adds
+ * jacobi_grid_add, jacobi_batched_stress and the jacobi_tune_* calls (and, in
+ * lbm.h, lbm_d3q19_blocked); 2: the pipelined plan takes jac_pipeline_t. */
 int jacobi_version(void);
 
 /* Description of the last failure on the calling thread ("" if none).  The

@@ -15,7 +15,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "jacobi.h")
 JAC_F32, JAC_F64 = 0, 1
 JAC_OK, JAC_EARG, JAC_EHIP, JAC_EWORKSPACE, JAC_EUNSUPPORTED = 0, -1, -2, -3, -4
 MAX_DEPTH = 8
-ABI_VERSION = 2
+ABI_VERSION = 3
 JAC_BATCH_RELAXED, JAC_BATCH_LOCKSTEP = 0, 1
 
 
@@ -118,11 +118,17 @@ def load():
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                            "or python paper_0912_4506_amd/csrc/build.py")
     lib = ctypes.CDLL(LIB_PATH)
+    missing = [name for name in SIGNATURES if not hasattr(lib, name)]
+    if missing:
+        raise RuntimeError(f"{LIB_PATH} lacks {', '.join(missing)}: it is older than this "
+                           "binding; rebuild it")
     for name, (args, res) in SIGNATURES.items():
-        if hasattr(lib, name):
-            f = getattr(lib, name)
-            f.argtypes = args
-            f.restype = res
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    if lib.jacobi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {lib.jacobi_version()}, this binding "
+                           f"needs {ABI_VERSION}; rebuild it")
     _lib = lib
     return lib
 

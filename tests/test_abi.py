@@ -20,7 +20,7 @@ def test_exports_every_declared_symbol(lib):
     missing = [s for s in declared if not hasattr(lib, s)]
     assert not missing, missing
     assert set(declared) == set(_lib.SIGNATURES), "binding and header disagree"
-    assert lib.jacobi_version() == 2
+    assert lib.jacobi_version() == 3
 
 
 P = ctypes.c_void_p
