@@ -7,8 +7,10 @@ benchmark times, compared over the whole grid.
   menu (the by-depth figures time each shape): bitwise, every cell, against
   the oracle's full run (about 2 s on the host).  The comparison runs on the
   GPU against an uploaded copy of the oracle's result.
-* The same grid by the pipelined schedule and in one array (the compressed
-  grid) at the configurations the benchmark reports, bitwise; and in FP32 at
+* The same grid by the pipelined schedule (the best configuration, two with
+  several passes in flight, and every setting of the looseness sweep) and in
+  one array (the compressed grid) at the configurations the benchmark
+  reports, bitwise; and in FP32 at
   the default blocking, every cell within 1e-5 of the FP64 oracle run on the
   FP32-rounded input.
 * 768^3, the refinement's inner solve: 50 FP32 sweeps with a right-hand side
@@ -105,6 +107,24 @@ def test_512_pipelined_full(jac, grid512, team, t, kchunk):
     torch.cuda.synchronize()
     assert not plan.wait_error()
     assert same_as(plan.results()[0], ref)
+
+
+@pytest.mark.parametrize("team,t,kchunk", [(4, 1, 16), (8, 1, 32), (4, 2, 32), (4, 4, 64)])
+def test_512_pipelined_looseness_full(jac, grid512, team, t, kchunk):
+    """Every setting of the benchmark's looseness sweep (Eq. 3): lower
+    distance 1 with upper distance 1 (lock step), 2, 4 and none, and upper
+    distance 2 with a team delay of 8 chunks, each over the whole grid.  The
+    waits change only the pacing: bitwise, and no wait gives up."""
+    u, ref = grid512
+    for du, dt in ((1, 0), (2, 0), (4, 0), (0, 0), (2, 8)):
+        a = dev(u)
+        b = torch.full_like(a, float("nan"))
+        plan = jac.PipelinePlan(a, b, T, team=team, t=t, kchunk=kchunk, dl=1, du=du, dt=dt)
+        plan.run("relaxed")
+        torch.cuda.synchronize()
+        assert not plan.wait_error(), (du, dt)
+        assert same_as(plan.results()[0], ref), (du, dt)
+        del a, b, plan
 
 
 @pytest.mark.parametrize("t", [4, 5])
