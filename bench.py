@@ -353,17 +353,24 @@ def bench_batched(args):
 
 
 def bench_adjoint(args):
+    """autograd forward + backward at 256^3, T = 32 (the backward is the
+    library's adjoint pass), FP64 and FP32, with and without checkpoints every
+    8 levels; and the adjoint call alone, whose blocked trace-mode pass is the
+    dominant kernel: its roofline at 16 B per cell and pass (FP64)."""
+    import math
     import torch
     from paper_0912_4506_amd import inputs, jacobi as jac
-    from paper_0912_4506_amd.autograd import JacobiT
-
-    from paper_0912_4506_amd.autograd import checkpoints
+    from paper_0912_4506_amd.autograd import JacobiT, checkpoints
 
     n, T, every = 256, 32, 8
     out = {"metric": "autograd forward+backward, 256^3, T=32, checkpoints every 8 levels",
-           "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": False, "dtype": "f64",
+           "data": "synthetic: uniform [0,1) grid, loss sum(w * A_T^2) with uniform [0,1) w",
+           "config": {"workload": f"jacobi3d {n}^3, T={T}, autograd with checkpoints every {every}"},
            "results": {}}
     for dt in (torch.float64, torch.float32):
+        name = "f64" if dt == torch.float64 else "f32"
         u = torch.from_numpy(inputs.grid(n, n, n, seed=0)).to("cuda", dt)
         w = torch.from_numpy(inputs.adjoint_weights(n, n, n, seed=0)).to("cuda", dt)
 
@@ -382,11 +389,31 @@ def bench_adjoint(args):
         a = u.clone()
         b = torch.empty_like(a)
         pms = time_steps(lambda: jac.plain(a, b, T), args.steps, 1)
-        out["results"]["f64" if dt == torch.float64 else "f32"] = {
+        # the adjoint call alone at the library's default blocking
+        lam = w.clone()
+        lb = torch.empty_like(lam)
+        ws = jac.adjoint_workspace(lam)
+        ams = time_steps(lambda: jac.adjoint(lam, lb, T, ws=ws), args.steps, args.warmup)
+        t = jac.default_tile(lam.shape, T, 0, dtype=dt)[0]
+        passes = math.ceil(T / t)
+        pass_bytes = 2 * n ** 3 * lam.element_size()
+        achieved = pass_bytes / (ams / passes * 1e-3) / 1e9
+        out["results"][name] = {
             "fwd_bwd_checkpointed_ms": round(cms, 3), "fwd_bwd_ms": round(ms, 3),
             "plain_forward_ms": round(pms, 3),
-            "ratio_to_plain_forward": round(cms / pms, 3)}
-    out["value"] = out["results"]["f64"]["fwd_bwd_checkpointed_ms"]
+            "ratio_to_plain_forward": round(cms / pms, 3),
+            "adjoint_ms": round(ams, 3), "adjoint_t": t, "adjoint_passes": passes,
+            "adjoint_glups": round(n ** 3 * T / (ams * 1e-3) / 1e9, 1),
+            "adjoint_achieved_gbs": round(achieved, 1)}
+        del u, w, a, b, lam, lb, ws
+        torch.cuda.empty_cache()
+    f64 = out["results"]["f64"]
+    out["value"] = f64["fwd_bwd_checkpointed_ms"]
+    out["ms_per_step"] = f64["fwd_bwd_checkpointed_ms"]
+    out["roofline"] = {"bound": "hbm", "kernel": "the adjoint's blocked trace-mode pass (FP64)",
+                       "achieved": f64["adjoint_achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(f64["adjoint_achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                       "algorithmic_bytes_per_launch": 2 * n ** 3 * 8}
     return out
 
 
@@ -445,9 +472,19 @@ def bench_pipelined(args):
     best = max(rows, key=lambda r: r["glups"])
     bms = time_steps(lambda: jac.tblock(a, b, T), args.steps, 1)
     pms = time_steps(lambda: jac.plain(a, b, T), max(1, args.steps // 2), 1)
+    # one persistent launch runs every pass: algorithmic traffic 16 B per
+    # cell and pass, over the launch's time
+    passes = math.ceil(T / best["t"])
+    achieved = 16 * N ** 3 * passes / (lups / (best["glups"] * 1e9)) / 1e9
     return {"metric": "GLUP/s, 512^3 FP64 Jacobi T=100, pipelined temporal blocking", "unit": "GLUP/s",
             "value": best["glups"], "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
+            "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(lups / (best["glups"] * 1e9) * 1e3, 3),
             "data": "synthetic: uniform [0,1) interior and shell, numpy default_rng(0)",
+            "roofline": {"bound": "hbm", "kernel": "batched_kernel, pipelined order (one launch, all passes)",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "algorithmic_bytes_per_launch": 16 * N ** 3 * passes},
             "config": {"workload": "jacobi3d 512^3 interior, FP64, T=100", **best},
             "overlapped_tiles_glups": round(lups / (bms * 1e-3) / 1e9, 1),
             "plain_glups": round(lups / (pms * 1e-3) / 1e9, 1),
@@ -581,11 +618,31 @@ def bench_refine(args):
                        "ms_per_50_sweeps": round(1e3 * sec * inner / max(sweeps, 1), 3),
                        "projected_seconds": round(sec * predicted / max(sweeps, 1), 1)}
         log(json.dumps({"fp64": res["fp64"]}))
+    # the dominant kernel: the inner FP32 sweeps with a right-hand side, alone
+    # (algorithmic traffic 12 B per cell and pass: e in and out, r in)
+    ea = torch.zeros(g.shape, dtype=torch.float32, device="cuda")
+    eb = torch.zeros_like(ea)
+    r32 = torch.rand(g.shape, dtype=torch.float32, device="cuda",
+                     generator=torch.Generator(device="cuda").manual_seed(0))
+    ims = time_steps(lambda: jac.tblock(ea, eb, inner, t=args.refine_t, rhs=r32), 5, 1)
+    it = jac.default_tile(g.shape, inner, args.refine_t, dtype=torch.float32, rhs=True)[0]
+    ipasses = math.ceil(inner / it)
+    iach = 12 * n ** 3 * ipasses / (ims * 1e-3) / 1e9
+    res["inner_solve"] = {"ms": round(ims, 3), "t": it, "passes": ipasses,
+                          "glups": round(n ** 3 * inner / (ims * 1e-3) / 1e9, 1),
+                          "achieved_gbs": round(iach, 1)}
+    del ea, eb, r32
     key = "projected_seconds" if bounded else "seconds"
     out = {"metric": f"Laplace solve {n}^3 to {tol:g} relative FP64 residual "
                      + ("(projected from a bounded run)" if bounded else "(wall clock)"),
            "unit": "s", "higher_is_better": False, "n_gpus": 1,
+           "dtype": "f32 inner sweeps, f64 residual and update",
+           "config": {"workload": f"Laplace {n}^3, tol {tol:g}, {inner} inner sweeps per outer step"},
            "data": "synthetic: uniform [0,1) Dirichlet data, zero initial interior",
+           "roofline": {"bound": "hbm", "kernel": "the inner FP32 blocked pass with a right-hand side",
+                        "achieved": round(iach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(iach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "algorithmic_bytes_per_launch": 12 * n ** 3},
            "results": res}
     if "mixed" in res:
         out["value"] = res["mixed"][key]

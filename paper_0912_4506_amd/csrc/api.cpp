@@ -402,13 +402,13 @@ bool tuned(int dtype, const Geo &g, int T, jac_tile_t *out)
 // What a blocking choice is for: the kind of kernel it selects.
 enum { KIND_PLAIN = 0, KIND_RHS = 1, KIND_TRACE = 2, KIND_BATCH = 3 };
 
-// Untuned default depth, from 512^3 (single grid), 768^3 (right-hand side)
-// and 64-grid batch runs on MI355X.
+// Untuned default depth, from 512^3 (single grid), 768^3 (right-hand side),
+// 256^3 adjoint and 64-grid batch runs on MI355X.
 int default_depth(int dtype, int kind)
 {
     if (dtype == JAC_F64)
         return kind == KIND_BATCH ? 5 : 4;
-    return kind == KIND_TRACE ? 6 : 5;
+    return kind == KIND_TRACE ? 2 : 5;
 }
 
 // Per-lane scratch bytes (register spills) of the kernel a choice selects;
@@ -424,7 +424,9 @@ int kind_scratch(int dtype, int kind, int cfg, int depth)
 
 // Block shapes measured fastest on MI355X at a given depth: 512^3 sweeps
 // without a right-hand side (T = 100; FP64 depth 5 also at 768^3, where it is
-// the best depth) and 768^3 FP32 sweeps with one (T = 50).
+// the best depth), 768^3 FP32 sweeps with one (T = 50) and adjoint passes at
+// 256^3 (T = 32: FP64 1.31 ms at depth 4 with 64x64 blocks of 16 waves, FP32
+// 0.95 ms at depth 2 with 64x48 blocks of 8).
 struct MeasuredShape {
     int dtype, kind, t, bx, by, waves;
 };
@@ -436,6 +438,8 @@ const MeasuredShape kMeasured[] = {
     {JAC_F32, KIND_PLAIN, 8, 64, 80, 16}, {JAC_F32, KIND_RHS, 4, 64, 80, 16},
     {JAC_F32, KIND_RHS, 5, 64, 80, 16},   {JAC_F32, KIND_RHS, 6, 64, 64, 16},
     {JAC_F32, KIND_RHS, 7, 64, 64, 16},   {JAC_F32, KIND_RHS, 8, 64, 64, 16},
+    // adjoint passes (trace mode), timed at 256^3, T = 32
+    {JAC_F64, KIND_TRACE, 4, 64, 64, 16}, {JAC_F32, KIND_TRACE, 2, 64, 48, 8},
 };
 
 // Untuned default block shape: the measured one for (dtype, kind, t) if there

@@ -123,16 +123,20 @@ def test_checkpoints_gradients(jac):
         assert np.array_equal(lv.detach().cpu().numpy(), oracle.sweeps(u, n))
 
 
-def test_config_256_t32_fp64_bitwise(jac):
-    """The differentiable workload's size: 256^3, T = 32, t = 8, FP64."""
+@pytest.mark.parametrize("t", [8, None])
+def test_config_256_t32_fp64_bitwise(jac, t):
+    """The differentiable workload's size: 256^3, T = 32, FP64, at t = 8 and
+    at the library's default blocking (what the benchmark's autograd run
+    uses)."""
     n, T = 256, 32
     lam = 2 * inputs.adjoint_weights(n, n, n, seed=0) * inputs.grid(n, n, n, seed=0)
     ref = oracle.adjoint(lam, T)
-    got = gpu_adjoint(jac, lam, T, t=8)
+    got = gpu_adjoint(jac, lam, T, t=t)
     assert np.array_equal(got, ref)
 
 
-def test_config_256_t32_fp32(jac):
+@pytest.mark.parametrize("t", [8, None])
+def test_config_256_t32_fp32(jac, t):
     """The differentiable workload in FP32: 256^3, T = 32, t = 8, against the
     oracle's FP64 adjoint of the FP32-rounded gradient.  The interior values
     are averages (bounded by the input's max); the shell gradient adds up to
@@ -140,5 +144,5 @@ def test_config_256_t32_fp32(jac):
     n, T = 256, 32
     lam = (2 * inputs.adjoint_weights(n, n, n, seed=0) * inputs.grid(n, n, n, seed=0)).astype(np.float32)
     ref = oracle.adjoint(lam.astype(np.float64), T)
-    got = gpu_adjoint(jac, lam, T, dtype=torch.float32, t=8)
+    got = gpu_adjoint(jac, lam, T, dtype=torch.float32, t=t)
     assert np.max(np.abs(got - ref)) <= 1e-5 * max(1.0, T / 6.0)
