@@ -104,3 +104,14 @@ def test_sweeps_to_tolerance_single_mode():
     want = math.ceil(math.log(tol) / math.log(abs(lam)) - 1e-9)
     assert pm.jacobi_sweeps_to_tolerance(x0, tol, modes=1) == want
     assert pm.jacobi_sweeps_to_tolerance(x0, tol, check_every=7) == -(-want // 7) * 7
+
+
+def test_host_copy_bandwidth_is_a_sane_rate(oracle_mod):
+    """The host copy probe behind the CPU baseline's P0 = M_s / 16 B: a
+    positive, finite rate below any host's memory bandwidth, and -1 for a
+    size or repeat count it cannot run."""
+    import math
+    ms = oracle_mod.copy_bandwidth(1 << 20, 3)
+    assert math.isfinite(ms) and 1e8 < ms < 1e13
+    assert oracle_mod._load().oracle_copy_bandwidth(0, 3, 1) == -1.0
+    assert oracle_mod._load().oracle_copy_bandwidth(1 << 10, 0, 1) == -1.0
