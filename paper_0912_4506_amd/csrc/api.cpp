@@ -1407,9 +1407,21 @@ static int build_plan(int dtype, int n, const jac_grid_t *g, void *const *a, voi
     }
     int it = 0;
     if (team == 0) {
+        // within a pass, the grids whose items stream the most planes first
+        // (longest processing time first): their next pass, which waits on
+        // them, then finds them done more often
+        std::vector<int> order(n);
+        for (int m = 0; m < n; ++m)
+            order[m] = m;
+        auto steps = [&](int m) {
+            return std::min<int64_t>(plans[m].tp.kchunk, plans[m].geo.nz) + 2 * (int64_t)tl.t;
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return steps(x) != steps(y) ? steps(x) > steps(y) : plans[x].tiles > plans[y].tiles;
+        });
         for (int pass = 0; pass < z.maxpasses; ++pass) {
             pass_start[pass] = it;
-            for (int m = 0; m < n; ++m) {
+            for (int m : order) {
                 if (pass >= plans[m].passes)
                     continue;
                 for (int tile_i = 0; tile_i < plans[m].tiles; ++tile_i)
