@@ -222,3 +222,18 @@ def test_grid_add_checks(lib):
     assert lib.jacobi_grid_add(1, ctypes.byref(g), None, B, None) == JAC_EARG and "dst" in err(lib)
     assert lib.jacobi_grid_add(5, ctypes.byref(g), A, B, None) == JAC_EARG
     assert lib.jacobi_grid_add(1, ctypes.byref(Grid(6, 6, 6, 7, 0)), A, B, None) == JAC_EARG
+
+
+def test_size_limits(lib):
+    """Extents above 2^28 and planes of 2 GiB or more are refused before any
+    HIP call (the kernels index planes and rows with 32-bit values)."""
+    big = Grid(1 << 28 | 1, 4, 4, 0, 0)
+    assert call_plain(lib, big) == JAC_EARG and "2^28" in err(lib)
+    wide = Grid(16384, 16384, 2, 0, 0)                 # 16386^2 doubles = 2.15 GB per plane
+    assert call_plain(lib, wide, a=P(1 << 40), b=P(1 << 44)) == JAC_EUNSUPPORTED
+    assert "2 GiB" in err(lib)
+    rc = lib.jacobi_tblock(1, ctypes.byref(wide), P(1 << 40), P(1 << 44), 4, None, None, None,
+                           ctypes.byref(OUT))
+    assert rc == JAC_EUNSUPPORTED and "2 GiB" in err(lib)
+    fits = Grid(16382, 16382, 2, 0, 0)                 # 16384^2 doubles: 2 GiB exactly
+    assert call_plain(lib, fits, a=P(1 << 40), b=P(1 << 44)) == JAC_EUNSUPPORTED

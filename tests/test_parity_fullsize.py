@@ -200,3 +200,23 @@ def test_768_residual_and_fused_update(jac):
                           r_ref[1:-1, 1:-1, 1:-1].astype(np.float32))
     assert math.isclose(norm2.item(), n2_ref, rel_tol=1e-12)
     assert torch.count_nonzero(z[1:-1, 1:-1, 1:-1]).item() == 0
+
+
+def test_largest_planes_bitwise(jac):
+    """Planes just under the 2 GiB the sweep kernels address with 32-bit
+    byte offsets (15402^2 doubles = 1.90 GB per plane, 3 interior planes):
+    the plain sweep and the blocked pass at its default blocking, every cell,
+    bitwise against the oracle."""
+    nx = ny = 15400
+    nz, T = 3, 4
+    assert (nx + 2) * (ny + 2) * 8 < 2 ** 31
+    u = inputs.grid(nx, ny, nz, seed=7)
+    ref = dev(oracle.sweeps(u, T))
+    for method in ("plain", "tblock"):
+        a = dev(u)
+        b = torch.full_like(a, float("nan"))
+        out = jac.plain(a, b, T) if method == "plain" else jac.tblock(a, b, T)
+        torch.cuda.synchronize()
+        assert same_as(out, ref), method
+        del a, b, out
+        torch.cuda.empty_cache()
