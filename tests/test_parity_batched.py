@@ -239,3 +239,20 @@ def test_batched_stress_bitwise(jac, mode, seed):
     assert not plan.wait_error()
     for m, (u, T, out) in enumerate(zip(us, Ts, plan.results())):
         assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T)), (m, mode, seed)
+
+
+@pytest.mark.parametrize("mode", ["relaxed", "lockstep"])
+def test_batched_zero_sweeps_and_single_cell(jac, mode):
+    """A grid with T = 0 keeps its input (no items), a 1-cell grid and a grid
+    thinner than a block run beside grids of many blocks."""
+    shapes = [(40, 30, 20), (1, 1, 1), (9, 2, 70), (130, 70, 33)]
+    Ts = [7, 5, 0, 12]
+    us, a, b = make_batch(shapes, seed=4)
+    plan = jac.BatchPlan(a, b, Ts, t=3, bx=64, by=48)
+    plan.run(mode)
+    torch.cuda.synchronize()
+    assert not plan.wait_error()
+    outs = plan.results()
+    assert outs[2].data_ptr() == a[2].data_ptr()
+    for m, (u, T, out) in enumerate(zip(us, Ts, outs)):
+        assert np.array_equal(out.cpu().numpy(), oracle.sweeps(u, T) if T else u), (m, mode)

@@ -306,3 +306,30 @@ def test_damaged_plan_images_are_refused(lib):
         assert lib.jacobi_batched_stress(img, len(img), 1, 4) == JAC_EARG
         assert lib.jacobi_batched_run(img, ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 34),
                                       1 << 20, 0, None) == JAC_EARG
+
+
+def test_batch_argument_checks(lib):
+    """Empty and oversized batches, missing arrays, a grid with T = 0 among
+    others (it keeps its input: no items, out_idx 0) and overlapping grids."""
+    g = (Grid * 2)(Grid(40, 30, 20, 0, 0), Grid(33, 17, 9, 0, 0))
+    T = (ctypes.c_int * 2)(6, 0)
+    tile = Tile(2, 64, 72, 16, 12)
+    assert lib.jacobi_batched_plan_bytes(1, 0, g, T, ctypes.byref(tile)) == 0
+    assert "batch size" in lib.jacobi_last_error().decode()
+    assert lib.jacobi_batched_plan_bytes(1, 70000, g, T, ctypes.byref(tile)) == 0
+    assert lib.jacobi_batched_plan_bytes(1, 2, None, T, ctypes.byref(tile)) == 0
+    nb = lib.jacobi_batched_plan_bytes(1, 2, g, T, ctypes.byref(tile))
+    assert nb > 0
+    buf = (ctypes.c_ubyte * nb)()
+    out = (ctypes.c_int * 2)(7, 7)
+    A = (ctypes.c_void_p * 2)(1 << 32, 3 << 32)
+    B = (ctypes.c_void_p * 2)(2 << 32, 4 << 32)
+    assert lib.jacobi_batched_plan(1, 2, g, A, B, T, ctypes.byref(tile), buf, nb, out) == 0
+    assert out[1] == 0
+    items = all_items(buf)
+    assert items and all(m == 0 for m, *_ in items)        # the T = 0 grid has no items
+    assert lib.jacobi_batched_plan(1, 2, g, A, B, T, ctypes.byref(tile), buf, nb - 16,
+                                   out) != 0
+    Bo = (ctypes.c_void_p * 2)(2 << 32, (1 << 32) + 4096)  # grid 1's b inside grid 0's a
+    assert lib.jacobi_batched_plan(1, 2, g, A, Bo, T, ctypes.byref(tile), buf, nb, out) == JAC_EARG
+    assert "overlap" in lib.jacobi_last_error().decode()
