@@ -456,17 +456,20 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
         // ---- publish the wave's first and last rows, then finish their P.
         // With one buffer, the old rows are read back before they are
         // overwritten, and a barrier keeps the previous step's readers safe.
+        // The wave's own previous edge rows (the D terms of its edge rows' P)
+        // are read before the barrier, so that only the neighbours' rows are
+        // read after it.  (With one buffer they must be: the slot is about to
+        // be overwritten.)
         real dold[TL][2][CI];
-        if constexpr (!DBUF) {
 #pragma unroll
-            for (int s = 0; s < TL; ++s)
+        for (int s = 0; s < TL; ++s)
 #pragma unroll
-                for (int c = 0; c < CI; ++c) {
-                    dold[s][0][c] = xold[xidx(w, 0, s, c, lane)];
-                    dold[s][1][c] = xold[xidx(w, 1, s, c, lane)];
-                }
+            for (int c = 0; c < CI; ++c) {
+                dold[s][0][c] = xold[xidx(w, 0, s, c, lane)];
+                dold[s][1][c] = xold[xidx(w, 1, s, c, lane)];
+            }
+        if constexpr (!DBUF)
             __syncthreads();
-        }
 #pragma unroll
         for (int s = 0; s < TL; ++s)
 #pragma unroll
@@ -477,12 +480,7 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                 }
             }
         __syncthreads();
-        auto dprev = [&](int side, int s, int c) -> real {
-            if constexpr (DBUF)
-                return xold[xidx(w, side, s, c, lane)];
-            else
-                return dold[s][side][c];
-        };
+        auto dprev = [&](int side, int s, int c) -> real { return dold[s][side][c]; };
 #pragma unroll
         for (int s = 0; s < TL; ++s) {
             if (s >= depth)
