@@ -470,6 +470,26 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
             }
         if constexpr (!DBUF)
             __syncthreads();
+        // the first term of the edge rows' P (west + east, from registers
+        // and DPP) before the barrier too: after it only the terms from the
+        // neighbouring waves remain
+        real we[TL][2][CI];
+#pragma unroll
+        for (int s = 0; s < TL; ++s) {
+            if (s >= depth)
+                break;
+            real west[CI], east[CI];
+            neighbours_i(Qo[s][0], west, east);
+#pragma unroll
+            for (int c = 0; c < CI; ++c)
+                we[s][0][c] = west[c] + east[c];
+            if constexpr (R > 1) {
+                neighbours_i(Qo[s][R - 1], west, east);
+#pragma unroll
+                for (int c = 0; c < CI; ++c)
+                    we[s][1][c] = west[c] + east[c];
+            }
+        }
 #pragma unroll
         for (int s = 0; s < TL; ++s)
 #pragma unroll
@@ -485,23 +505,20 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
         for (int s = 0; s < TL; ++s) {
             if (s >= depth)
                 break;
-            real west[CI], east[CI];
-            neighbours_i(Qo[s][0], west, east);
 #pragma unroll
             for (int c = 0; c < CI; ++c) {
                 const real sn = xcur[xidx(wa, 1, s, c, lane)];
                 const real north = R > 1 ? Qo[s][R > 1 ? 1 : 0][c] : xcur[xidx(wb, 0, s, c, lane)];
-                real q = west[c] + east[c];
+                real q = we[s][0][c];
                 q = q + sn;
                 q = q + north;
                 P[s][0][c] = q + dprev(0, s, c);
             }
             if constexpr (R > 1) {
-                neighbours_i(Qo[s][R - 1], west, east);
 #pragma unroll
                 for (int c = 0; c < CI; ++c) {
                     const real nn = xcur[xidx(wb, 0, s, c, lane)];
-                    real q = west[c] + east[c];
+                    real q = we[s][1][c];
                     q = q + Qo[s][R - 2][c];
                     q = q + nn;
                     P[s][R - 1][c] = q + dprev(1, s, c);
