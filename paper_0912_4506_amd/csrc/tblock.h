@@ -348,12 +348,29 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                 Qo[0][r][c] = cur[r][c];
         trace_level(0, k, Qo[0]);
 
+        // With two slabs, a level's edge rows go to LDS as soon as the level
+        // is complete (every reader of this slab passed the previous
+        // barrier), so the writes overlap the remaining levels.
+        const int par = DBUF ? (k & 1) : 0;
+        real *xcur = xch + par * XSLAB;
+        auto publish = [&](int s) {
+            if constexpr (DBUF) {
+#pragma unroll
+                for (int c = 0; c < CI; ++c) {
+                    xcur[xidx(w, 0, s, c, lane)] = Qo[s][0][c];
+                    xcur[xidx(w, 1, s, c, lane)] = Qo[s][R - 1][c];
+                }
+            } else {
+                (void)s;
+            }
+        };
+        if (depth > 0)
+            publish(0);
+
         // ---- complete one plane per level, back to back; right after level s
         // completes, advance P[s-1] for the rows whose j-neighbours are in
         // registers.  The wave's first and last rows are finished after the
         // exchange; their Q values live in LDS (own slot, previous parity).
-        const int par = DBUF ? (k & 1) : 0;
-        real *xcur = xch + par * XSLAB;
         const real *xold = xch + (DBUF ? (par ^ 1) : 0) * XSLAB;
 #pragma unroll
         for (int s = 1; s <= TL; ++s) {
@@ -403,6 +420,7 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                     for (int c = 0; c < CI; ++c)
                         Qo[s < TL ? s : 0][r][c] = o[r][c];
                 trace_level(s, plane, Qo[s < TL ? s : 0]);
+                publish(s < TL ? s : 0);
             } else if constexpr (MODE == MODE_BATCH) {
                 if (plane >= k0 && plane < k1) {
                     real *dplane = p.dst + (int64_t)plane * p.sz;
@@ -490,15 +508,17 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                     we[s][1][c] = west[c] + east[c];
             }
         }
+        if constexpr (!DBUF) {
 #pragma unroll
-        for (int s = 0; s < TL; ++s)
+            for (int s = 0; s < TL; ++s)
 #pragma unroll
-            for (int c = 0; c < CI; ++c) {
-                if (s < depth) {
-                    xcur[xidx(w, 0, s, c, lane)] = Qo[s][0][c];
-                    xcur[xidx(w, 1, s, c, lane)] = Qo[s][R - 1][c];
+                for (int c = 0; c < CI; ++c) {
+                    if (s < depth) {
+                        xcur[xidx(w, 0, s, c, lane)] = Qo[s][0][c];
+                        xcur[xidx(w, 1, s, c, lane)] = Qo[s][R - 1][c];
+                    }
                 }
-            }
+        }
         __syncthreads();
         auto dprev = [&](int side, int s, int c) -> real { return dold[s][side][c]; };
 #pragma unroll
