@@ -408,7 +408,7 @@ int default_depth(int dtype, int kind)
 {
     if (dtype == JAC_F64)
         return kind == KIND_BATCH ? 5 : 4;
-    return kind == KIND_TRACE ? 2 : 5;
+    return kind == KIND_TRACE ? 2 : kind == KIND_PLAIN ? 6 : kind == KIND_RHS ? 7 : 5;
 }
 
 // Per-lane scratch bytes (register spills) of the kernel a choice selects;
@@ -433,10 +433,10 @@ struct MeasuredShape {
 const MeasuredShape kMeasured[] = {
     {JAC_F64, KIND_PLAIN, 3, 64, 64, 8},  {JAC_F64, KIND_PLAIN, 4, 64, 72, 12},
     {JAC_F64, KIND_PLAIN, 5, 64, 60, 12}, {JAC_F64, KIND_PLAIN, 6, 64, 48, 8},
-    {JAC_F32, KIND_PLAIN, 4, 64, 60, 12}, {JAC_F32, KIND_PLAIN, 5, 64, 64, 16},
+    {JAC_F32, KIND_PLAIN, 4, 64, 72, 12}, {JAC_F32, KIND_PLAIN, 5, 64, 80, 16},
     {JAC_F32, KIND_PLAIN, 6, 64, 80, 16}, {JAC_F32, KIND_PLAIN, 7, 64, 80, 16},
-    {JAC_F32, KIND_PLAIN, 8, 64, 80, 16}, {JAC_F32, KIND_RHS, 4, 64, 80, 16},
-    {JAC_F32, KIND_RHS, 5, 64, 80, 16},   {JAC_F32, KIND_RHS, 6, 64, 64, 16},
+    {JAC_F32, KIND_PLAIN, 8, 64, 80, 16}, {JAC_F32, KIND_RHS, 4, 64, 56, 8},
+    {JAC_F32, KIND_RHS, 5, 64, 60, 12},   {JAC_F32, KIND_RHS, 6, 64, 60, 12},
     {JAC_F32, KIND_RHS, 7, 64, 64, 16},   {JAC_F32, KIND_RHS, 8, 64, 64, 16},
     // adjoint passes (trace mode), timed at 256^3, T = 32
     {JAC_F64, KIND_TRACE, 4, 64, 64, 16}, {JAC_F32, KIND_TRACE, 2, 64, 48, 8},
