@@ -394,7 +394,7 @@ def bench_adjoint(args):
         lb = torch.empty_like(lam)
         ws = jac.adjoint_workspace(lam)
         ams = time_steps(lambda: jac.adjoint(lam, lb, T, ws=ws), args.steps, args.warmup)
-        t = jac.default_tile(lam.shape, T, 0, dtype=dt)[0]
+        t = jac.default_tile(lam.shape, T, 0, dtype=dt, adjoint=True)[0]
         passes = math.ceil(T / t)
         pass_bytes = 2 * n ** 3 * lam.element_size()
         achieved = pass_bytes / (ams / passes * 1e-3) / 1e9
@@ -738,7 +738,7 @@ def main():
                     help="batched: time the relaxed graph replay only (no lockstep or per-grid runs)")
     ap.add_argument("--refine-n", type=int, default=768)
     ap.add_argument("--refine-tol", type=float, default=1e-10)
-    ap.add_argument("--refine-t", type=int, default=8,
+    ap.add_argument("--refine-t", type=int, default=0,
                     help="inner FP32 sweeps per pass (0: the library's choice)")
     ap.add_argument("--refine-outer", type=int, default=0,
                     help="> 0: bounded run of that many outer iterations, time projected")

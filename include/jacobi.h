@@ -387,12 +387,13 @@ int jacobi_tune_forget(void);
  * returns the number available. */
 int jacobi_tile_menu(int dtype, int *shapes_host, int cap);
 
-/* The tile jacobi_tblock uses for (dtype, g, T, t) when tile fields are 0
- * (t = 0: library choice of t as well); rhs != 0 asks for the choice made
- * when a right-hand side is passed (those kernels hold one more value per
- * cell and level, so their register budget differs).  Only nx, ny, nz of *g
- * are read.  Writes *tile_host; returns JAC_OK. */
-int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, int rhs,
+/* The tile a call makes for (dtype, g, T, t) when tile fields are 0 (t = 0:
+ * library choice of t as well).  kind 0: jacobi_tblock without a right-hand
+ * side; 1: jacobi_tblock with one (those kernels hold one more value per cell
+ * and level, so their register budget differs); 2: jacobi_adjoint (the trace
+ * pass records the shell faces, a budget of its own).  Only nx, ny, nz of *g
+ * are read.  Writes *tile_host; returns JAC_OK, or JAC_EARG for another kind. */
+int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, int kind,
                         jac_tile_t *tile_host);
 
 #ifdef __cplusplus

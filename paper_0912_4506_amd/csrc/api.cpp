@@ -1914,7 +1914,7 @@ int jacobi_tile_menu(int dtype, int *shapes_host, int cap)
     return kMenuN;
 }
 
-int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, int rhs, jac_tile_t *tile_host)
+int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, int kind, jac_tile_t *tile_host)
 {
     g_err.clear();
     Geo geo;
@@ -1925,9 +1925,14 @@ int jacobi_default_tile(int dtype, const jac_grid_t *g, int T, int t, int rhs, j
         return fail(JAC_EARG, "tile_host is NULL");
     if (T < 0)
         return fail(JAC_EARG, "T = %d is negative", T);
+    if (kind < 0 || kind > 2)
+        return fail(JAC_EARG, "kind = %d is not 0 (plain), 1 (right-hand side) or 2 (adjoint)",
+                    kind);
+    // the same resolution as jacobi_tblock and jacobi_adjoint: only the plain
+    // pass consults the tuning cache, which is keyed by its geometry
+    const int k = kind == 2 ? KIND_TRACE : kind == 1 ? KIND_RHS : KIND_PLAIN;
     jac_tile_t req{t, 0, 0, 0, 0};
-    if ((rc = resolve_tile(dtype, &req, T, tile_host, rhs ? nullptr : &geo,
-                           rhs ? KIND_RHS : KIND_PLAIN)))
+    if ((rc = resolve_tile(dtype, &req, T, tile_host, k == KIND_PLAIN ? &geo : nullptr, k)))
         return rc;
     return JAC_OK;
 }

@@ -102,14 +102,14 @@ def tile_menu(dtype=torch.float64):
     return [(buf[3 * m], buf[3 * m + 1], buf[3 * m + 2]) for m in range(min(n, 64))]
 
 
-def default_tile(shape, T, t=0, dtype=torch.float64, rhs=False):
+def default_tile(shape, T, t=0, dtype=torch.float64, rhs=False, adjoint=False):
     """Library choice of (t, bx, by, kchunk, waves) for a (nz+2, ny+2, nx+2)
-    grid (rhs: for sweeps with a right-hand side)."""
+    grid (rhs: for sweeps with a right-hand side; adjoint: for adjoint())."""
     nz, ny, nx = (s - 2 for s in shape)
     tile = Tile()
+    kind = 2 if adjoint else int(bool(rhs))
     check(_lib.load().jacobi_default_tile(_DTYPES[dtype], ctypes.byref(Grid(nx, ny, nz, 0, 0)),
-                                          int(T), int(t or 0), int(bool(rhs)),
-                                          ctypes.byref(tile)))
+                                          int(T), int(t or 0), kind, ctypes.byref(tile)))
     return tile.t, tile.bx, tile.by, tile.kchunk, tile.waves
 
 

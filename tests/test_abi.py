@@ -82,10 +82,14 @@ def test_menu_and_default_tile(lib):
     assert all(bx % 64 == 0 and by > 0 and w in (4, 8, 12, 16) for bx, by, w in shapes)
     assert len(set(shapes)) == len(shapes)
     t = Tile()
-    for rhs in (0, 1):
-        assert lib.jacobi_default_tile(1, ctypes.byref(Grid(512, 512, 512, 0, 0)), 100, 0, rhs,
+    for kind in (0, 1, 2):
+        assert lib.jacobi_default_tile(1, ctypes.byref(Grid(512, 512, 512, 0, 0)), 100, 0, kind,
                                        ctypes.byref(t)) == 0
         assert 1 <= t.t <= 8 and (t.bx, t.by, t.waves) in shapes
+    for kind in (-1, 3):
+        assert lib.jacobi_default_tile(1, ctypes.byref(Grid(512, 512, 512, 0, 0)), 100, 0, kind,
+                                       ctypes.byref(t)) == -1
+        assert b"kind" in lib.jacobi_last_error()
     # depth never exceeds the sweep count
     assert lib.jacobi_default_tile(1, ctypes.byref(Grid(9, 9, 9, 0, 0)), 3, 8, 0,
                                    ctypes.byref(t)) == 0

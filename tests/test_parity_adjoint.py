@@ -146,3 +146,21 @@ def test_config_256_t32_fp32(jac, t):
     ref = oracle.adjoint(lam.astype(np.float64), T)
     got = gpu_adjoint(jac, lam, T, dtype=torch.float32, t=t)
     assert np.max(np.abs(got - ref)) <= 1e-5 * max(1.0, T / 6.0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("T", [7, 32])
+def test_default_tile_reports_the_adjoints_choice(jac, dtype, T):
+    """default_tile(adjoint=True) names the blocking adjoint() takes when left
+    to the library: the returned buffer follows the parity of ceil(T / t),
+    and the result is bitwise that of the same blocking passed explicitly."""
+    n = 70
+    lam = 2 * inputs.adjoint_weights(n, n, n, seed=3) * inputs.grid(n, n, n, seed=3)
+    t, bx, by, _, waves = jac.default_tile(lam.shape, T, dtype=dtype, adjoint=True)
+    a = dev(lam, dtype)
+    b = torch.zeros_like(a)
+    out = jac.adjoint(a, b, T)
+    assert out is (b if -(-T // t) % 2 else a)
+    got = out.cpu().numpy()
+    want = gpu_adjoint(jac, lam, T, dtype=dtype, t=t, bx=bx, by=by, waves=waves)
+    assert np.array_equal(got.astype(np.float64), want)
