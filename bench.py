@@ -632,6 +632,18 @@ def bench_refine(args):
                           "glups": round(n ** 3 * inner / (ims * 1e-3) / 1e9, 1),
                           "achieved_gbs": round(iach, 1)}
     del ea, eb, r32
+    torch.cuda.empty_cache()
+    # HBM traffic of that kernel from its committed profile (rocprofv3
+    # FETCH_SIZE/WRITE_SIZE scaled by the copy kernel's), while the kernel
+    # sources and the default blocking are those it was measured on
+    res["copy_bandwidth_gbs"] = round(copy_bandwidth(jac), 1)
+    # (the passes' depths differ by at most one: the profile covers the
+    # depth most of them run at)
+    _, ibx, iby, _, iw = jac.default_tile(g.shape, inner, args.refine_t, dtype=torch.float32, rhs=True)
+    base, rem = divmod(inner, ipasses)
+    idepth = base + 1 if rem > ipasses - rem else base
+    fig = profile_figures(f"refine_{n}cubed.md",
+                          f"tblock_kernel<float, {idepth}, {ibx // 64}, {iby // iw}, {iw}, 1>")
     key = "projected_seconds" if bounded else "seconds"
     out = {"metric": f"Laplace solve {n}^3 to {tol:g} relative FP64 residual "
                      + ("(projected from a bounded run)" if bounded else "(wall clock)"),
@@ -641,7 +653,9 @@ def bench_refine(args):
            "data": "synthetic: uniform [0,1) Dirichlet data, zero initial interior",
            "roofline": {"bound": "hbm", "kernel": "the inner FP32 blocked pass with a right-hand side",
                         "achieved": round(iach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(iach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "frac": round(iach / HBM_PEAK_GBS, 4),
+                        "traffic": fig.get("traffic_gb_per_launch") if fig else None,
+                        "traffic_unit": f"GB per launch (the depth-{idepth} passes)",
                         "algorithmic_bytes_per_launch": 12 * n ** 3},
            "results": res}
     if "mixed" in res:
