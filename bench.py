@@ -63,6 +63,13 @@ DEPTH_REFUSAL = {16: " (the blocked pass keeps about two values per cell and lev
                      "depth 8 already spills on blocks with useful halo overhead)"}
 
 
+def dominant_depth(T, passes):
+    """The depth most of the passes of a T-sweep run run at (the library
+    splits T into passes whose depths differ by at most one)."""
+    base, rem = divmod(T, passes)
+    return base + 1 if rem > passes - rem else base
+
+
 def ensure_built():
     from paper_0912_4506_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
@@ -410,9 +417,20 @@ def bench_adjoint(args):
     f64 = out["results"]["f64"]
     out["value"] = f64["fwd_bwd_checkpointed_ms"]
     out["ms_per_step"] = f64["fwd_bwd_checkpointed_ms"]
+    # HBM traffic of the FP64 trace-mode pass from its committed profile
+    # (rocprofv3 FETCH_SIZE/WRITE_SIZE scaled by the copy kernel's), for the
+    # depth most passes run at
+    out["copy_bandwidth_gbs"] = round(copy_bandwidth(jac), 1)
+    t, bx, by, _, w = jac.default_tile((n + 2,) * 3, T, 0, dtype=torch.float64, adjoint=True)
+    passes = math.ceil(T / t)
+    fig = profile_figures(f"adjoint_f64_{n}cubed.md",
+                          f"tblock_kernel<double, {dominant_depth(T, passes)}, {bx // 64}, "
+                          f"{by // w}, {w}, 2>")
     out["roofline"] = {"bound": "hbm", "kernel": "the adjoint's blocked trace-mode pass (FP64)",
                        "achieved": f64["adjoint_achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(f64["adjoint_achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                       "frac": round(f64["adjoint_achieved_gbs"] / HBM_PEAK_GBS, 4),
+                       "traffic": fig.get("traffic_gb_per_launch") if fig else None,
+                       "traffic_unit": "GB per launch",
                        "algorithmic_bytes_per_launch": 2 * n ** 3 * 8}
     return out
 
@@ -640,8 +658,7 @@ def bench_refine(args):
     # (the passes' depths differ by at most one: the profile covers the
     # depth most of them run at)
     _, ibx, iby, _, iw = jac.default_tile(g.shape, inner, args.refine_t, dtype=torch.float32, rhs=True)
-    base, rem = divmod(inner, ipasses)
-    idepth = base + 1 if rem > ipasses - rem else base
+    idepth = dominant_depth(inner, ipasses)
     fig = profile_figures(f"refine_{n}cubed.md",
                           f"tblock_kernel<float, {idepth}, {ibx // 64}, {iby // iw}, {iw}, 1>")
     key = "projected_seconds" if bounded else "seconds"

@@ -145,7 +145,9 @@ int jacobi_tblock(int dtype, const jac_grid_t *g, void *a, void *b, int T,
  * lam_b: second grid of the pair (contents ignored).  ws: device workspace
  * of at least jacobi_adjoint_workspace(dtype, g, t) bytes (t as in tile,
  * 0 = library choice), aligned to the element size, not overlapping the grids.
- * T = 0 enqueues nothing: the input is the gradient (*out_idx = 0). */
+ * T = 0 enqueues nothing: the input is the gradient (*out_idx = 0).  T > 0
+ * returns JAC_EUNSUPPORTED, before any launch, when one level of face values
+ * (2(ny nz + nx nz + nx ny) elements) takes 2 GiB or more. */
 /* dst += src on every element of a grid, shell included, one rounding per
  * element.  It is the step between two adjoint segments when a loss also
  * depends on an intermediate level s: the gradient arriving at level s is

@@ -408,7 +408,7 @@ int default_depth(int dtype, int kind)
 {
     if (dtype == JAC_F64)
         return kind == KIND_BATCH ? 5 : 4;
-    return kind == KIND_TRACE ? 2 : kind == KIND_PLAIN ? 6 : kind == KIND_RHS ? 7 : 5;
+    return kind == KIND_TRACE ? 3 : kind == KIND_PLAIN ? 6 : kind == KIND_RHS ? 7 : 5;
 }
 
 // Per-lane scratch bytes (register spills) of the kernel a choice selects;
@@ -425,8 +425,8 @@ int kind_scratch(int dtype, int kind, int cfg, int depth)
 // Block shapes measured fastest on MI355X at a given depth: 512^3 sweeps
 // without a right-hand side (T = 100; FP64 depth 5 also at 768^3, where it is
 // the best depth), 768^3 FP32 sweeps with one (T = 50) and adjoint passes at
-// 256^3 (T = 32: FP64 1.31 ms at depth 4 with 64x64 blocks of 16 waves, FP32
-// 0.95 ms at depth 2 with 64x48 blocks of 8).
+// 256^3 (T = 32: FP64 1.23 ms at depth 4 with 64x60 blocks of 12 waves, FP32
+// 0.76 ms at depth 3 with the same blocks).
 struct MeasuredShape {
     int dtype, kind, t, bx, by, waves;
 };
@@ -439,7 +439,8 @@ const MeasuredShape kMeasured[] = {
     {JAC_F32, KIND_RHS, 5, 64, 60, 12},   {JAC_F32, KIND_RHS, 6, 64, 60, 12},
     {JAC_F32, KIND_RHS, 7, 64, 64, 16},   {JAC_F32, KIND_RHS, 8, 64, 64, 16},
     // adjoint passes (trace mode), timed at 256^3, T = 32
-    {JAC_F64, KIND_TRACE, 4, 64, 64, 16}, {JAC_F32, KIND_TRACE, 2, 64, 48, 8},
+    {JAC_F64, KIND_TRACE, 4, 64, 60, 12}, {JAC_F32, KIND_TRACE, 2, 64, 60, 12},
+    {JAC_F32, KIND_TRACE, 3, 64, 60, 12},
 };
 
 // Untuned default block shape: the measured one for (dtype, kind, t) if there
@@ -1044,6 +1045,10 @@ int jacobi_adjoint(int dtype, const jac_grid_t *g, void *lam_a, void *lam_b, int
     *out_idx = 0;
     if (T == 0)
         return JAC_OK;  // the gradient w.r.t. level 0 is the input itself
+    // the trace pass addresses one level of face values with 32-bit byte offsets
+    if (face_count(geo) * (int64_t)elem_size(dtype) > INT_MAX)
+        return fail(JAC_EUNSUPPORTED, "one level of shell faces (%lld values) takes 2 GiB or more",
+                    (long long)face_count(geo));
     const size_t need = adjoint_ws_bytes(dtype, geo, tl.t);
     if (!ws)
         return fail(JAC_EWORKSPACE, "workspace is NULL (%zu bytes needed)", need);

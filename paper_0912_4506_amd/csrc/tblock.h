@@ -173,10 +173,14 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
         if constexpr (MODE == MODE_TRACE) {
             if (plane < k0 || plane >= k1)
                 return;
-            real *tr = p.trace + (int64_t)s * p.fstride;
-            const int64_t nyz = (int64_t)p.ny * p.nz, nxz = (int64_t)p.nx * p.nz;
-            const int64_t nxy = (int64_t)p.nx * p.ny;
-            real *fi = tr, *fj = tr + 2 * nyz, *fk = tr + 2 * nyz + 2 * nxz;
+            // One buffer resource per level and 32-bit byte offsets (the host
+            // keeps a level of faces below 2^31 bytes): the row and plane
+            // parts of an offset are wave-uniform, only the i part is per
+            // lane, so the recording holds few registers across the loop.
+            constexpr int E = (int)sizeof(real);
+            const auto rs = plane_rsrc(p.trace + (int64_t)s * p.fstride, (int)(p.fstride * E));
+            const int nyz = p.ny * p.nz, nxz = p.nx * p.nz, nxy = p.nx * p.ny;
+            const int fj0 = 2 * nyz, fk0 = 2 * nyz + 2 * nxz;
             const bool klo = plane == 1, khi = plane == p.nz;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -185,31 +189,32 @@ __device__ __forceinline__ void tb_tile(const TbArgs<real> &p, int ti, int tj, i
                 const int j = jrow[r];
                 const bool jlo = j == 1, jhi = j == p.ny;
                 if (klo || khi || jlo || jhi) {
+                    const int kb = fk0 + (j - 1) * p.nx, jb = fj0 + (plane - 1) * p.nx;
 #pragma unroll
                     for (int c = 0; c < CI; ++c) {
                         if (!ok_i[c])
                             continue;
-                        const int i = ic[c];
+                        const int i = ic[c] - 1;
                         if (klo)
-                            fk[(int64_t)(j - 1) * p.nx + (i - 1)] = v[r][c];
+                            plane_store(v[r][c], rs, (kb + i) * E);
                         if (khi)
-                            fk[nxy + (int64_t)(j - 1) * p.nx + (i - 1)] = v[r][c];
+                            plane_store(v[r][c], rs, (kb + nxy + i) * E);
                         if (jlo)
-                            fj[(int64_t)(plane - 1) * p.nx + (i - 1)] = v[r][c];
+                            plane_store(v[r][c], rs, (jb + i) * E);
                         if (jhi)
-                            fj[nxz + (int64_t)(plane - 1) * p.nx + (i - 1)] = v[r][c];
+                            plane_store(v[r][c], rs, (jb + nxz + i) * E);
                     }
                 }
                 if (fix_i) {
+                    const int ib = (plane - 1) * p.ny + (j - 1);
 #pragma unroll
                     for (int c = 0; c < CI; ++c) {
                         if (!ok_i[c])
                             continue;
-                        const int i = ic[c];
-                        if (i == 1)
-                            fi[(int64_t)(plane - 1) * p.ny + (j - 1)] = v[r][c];
-                        if (i == p.nx)
-                            fi[nyz + (int64_t)(plane - 1) * p.ny + (j - 1)] = v[r][c];
+                        if (ic[c] == 1)
+                            plane_store(v[r][c], rs, ib * E);
+                        if (ic[c] == p.nx)
+                            plane_store(v[r][c], rs, (nyz + ib) * E);
                     }
                 }
             }

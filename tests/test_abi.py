@@ -110,6 +110,24 @@ def test_adjoint_workspace_checks(lib):
     assert rc == JAC_EWORKSPACE and "needed" in err(lib)
 
 
+def test_adjoint_refuses_faces_beyond_2gib(lib):
+    """The trace pass addresses one level of shell faces with 32-bit byte
+    offsets: a grid whose faces take 2 GiB or more per level is refused
+    before anything is enqueued (here 2 (ny nz + nx nz + nx ny) > 2^28)."""
+    g = Grid(8, 1 << 14, 1 << 14, 0, 0)
+    tile = Tile(4, 0, 0, 0, 0)
+    rc = lib.jacobi_adjoint(1, ctypes.byref(g), P(1 << 40), P(1 << 44), 5, ctypes.byref(tile),
+                            None, 0, None, ctypes.byref(OUT))
+    assert rc == JAC_EUNSUPPORTED and "2 GiB" in err(lib)
+    # FP32 halves the bytes: 2^29 values * 4 B is still 2 GiB
+    rc = lib.jacobi_adjoint(0, ctypes.byref(g), P(1 << 40), P(1 << 44), 5, ctypes.byref(tile),
+                            None, 0, None, ctypes.byref(OUT))
+    assert rc == JAC_EUNSUPPORTED
+    # T = 0 is the identity and needs no trace
+    assert lib.jacobi_adjoint(1, ctypes.byref(g), P(1 << 40), P(1 << 44), 0, ctypes.byref(tile),
+                              None, 0, None, ctypes.byref(OUT)) == 0
+
+
 def test_residual_and_copy_checks(lib):
     g = Grid(10, 10, 10, 0, 0)
     n2 = P(1 << 36)

@@ -67,3 +67,14 @@ def test_ambiguous_kernel_is_an_error(runs):
 def test_source_hash_is_stable():
     assert profiling.kernel_source_hash() == profiling.kernel_source_hash()
     assert len(profiling.kernel_source_hash()) == 16
+
+
+def test_dominant_depth():
+    """The depth most passes run at when T sweeps are split into passes whose
+    depths differ by at most one (the library's pass planner)."""
+    import bench
+    assert bench.dominant_depth(50, 8) == 6      # 6 passes of 6, 2 of 7
+    assert bench.dominant_depth(50, 7) == 7      # 6 of 7, 1 of 8
+    assert bench.dominant_depth(100, 25) == 4
+    assert bench.dominant_depth(32, 8) == 4
+    assert bench.dominant_depth(11, 3) == 4      # 4, 4, 3
