@@ -11,16 +11,21 @@ of the next; the work does not depend on the values).
                 (16 B per cell per pass, one read and one write of each cell)
                 over its average launch duration (HIP events on the stream the
                 kernels run on), against the 8 TB/s HBM peak; `traffic` is the
-                measured HBM traffic per launch when given with --traffic
+                measured HBM traffic per launch from the committed rocprofv3
+                summary of that kernel (or --traffic), null once the kernel
+                sources differ from those it was measured on
   plain         the plain one-pass-per-sweep kernel under the same protocol
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
 
 Other workloads (--workload): `batched` (64 grids, edges log-uniform in
-[32, 256], T = 50, one persistent launch), `adjoint` (256^3, T = 32, t = 8,
-forward + backward), `refine` (768^3 Laplace solve, FP32 inner / FP64 outer,
-vs all-FP64 Jacobi; runs many minutes), `pipelined` (512^3, T = 100, by the
-pipelined schedule, with the looseness sweep of Eq. 3), `compressed` (512^3,
-T = 100, in one array), `lbm` (D3Q19 lattice Boltzmann, 256^3, FP64 and FP32).
+[32, 256], T = 50, one persistent launch), `adjoint` (256^3, T = 32,
+autograd forward + backward and the adjoint call alone), `refine` (768^3
+Laplace solve, FP32 inner / FP64 outer, vs all-FP64 Jacobi; runs many
+minutes, or --refine-outer K for a bounded run), `pipelined` (512^3, T = 100,
+by the pipelined schedule, with the looseness sweep of Eq. 3), `compressed`
+(512^3, T = 100, in one array), `lbm` (D3Q19 lattice Boltzmann, 256^3, FP64
+and FP32), `fp32` (the blocked pass in FP32 at 512^3, T = 100, and with a
+right-hand side at 768^3, T = 50, every depth).
 """
 import argparse
 import json
@@ -682,6 +687,56 @@ def bench_refine(args):
     return out
 
 
+def bench_fp32(args):
+    """The blocked pass in FP32: 512^3, T = 100 (8 B per cell and pass) and
+    the refinement's inner form, 768^3, T = 50 with a right-hand side (12 B
+    per cell and pass), each at the library's default blocking of every depth
+    2..8 and at its default depth.  The input is the FP64 workload's seeded
+    grid cast to FP32; the right-hand side is uniform [0, 1)."""
+    import torch
+    from paper_0912_4506_amd import inputs, jacobi as jac
+
+    f32 = torch.float32
+
+    def sweep(n, T, rhs, bytes_per_cell):
+        a = torch.from_numpy(inputs.grid(n, n, n, seed=0)).to("cuda", f32)
+        b = torch.empty_like(a)
+        r = (torch.rand(a.shape, dtype=f32, device="cuda",
+                        generator=torch.Generator(device="cuda").manual_seed(0)) if rhs else None)
+        rows = {}
+        for t in range(2, 9):
+            tt, bx, by, _, w = jac.default_tile(a.shape, T, t, dtype=f32, rhs=rhs)
+            try:
+                ms = time_steps(lambda: jac.tblock(a, b, T, t=tt, bx=bx, by=by, waves=w, rhs=r),
+                                args.steps, args.warmup)
+            except Exception as e:                # a depth the menu cannot run
+                rows[str(t)] = f"refused: {e}"
+                continue
+            passes = math.ceil(T / tt)
+            rows[str(t)] = {"glups": round(n ** 3 * T / (ms * 1e-3) / 1e9, 1), "tile": [bx, by],
+                            "waves": w, "passes": passes,
+                            "achieved_gbs": round(bytes_per_cell * n ** 3 * passes / (ms * 1e-3) / 1e9, 1)}
+        d = jac.default_tile(a.shape, T, 0, dtype=f32, rhs=rhs)
+        del a, b, r
+        torch.cuda.empty_cache()
+        return rows, d
+
+    rows, d = sweep(512, 100, False, 8)
+    best = rows[str(d[0])]
+    rrows, rd = sweep(768, 50, True, 12)
+    return {"metric": "GLUP/s, 512^3 FP32 Jacobi T=100, temporal-blocked", "value": best["glups"],
+            "unit": "GLUP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic: the FP64 workload's uniform [0,1) grid cast to FP32",
+            "config": {"workload": "jacobi3d 512^3 interior, FP32, T=100", "t": d[0],
+                       "tile_bx_by": [d[1], d[2]], "waves": d[4]},
+            "roofline": {"bound": "hbm", "achieved": best["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(best["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                         "traffic": None, "algorithmic_bytes_per_launch": 8 * 512 ** 3},
+            "by_depth": rows,
+            "rhs_768": {"T": 50, "default_t": rd[0], "by_depth": rrows}}
+
+
 def bench_lbm(args):
     """D3Q19 lattice Boltzmann (BGK, periodic 256^3 box, omega = 1.7): the
     fused pull stream-collide kernel (one step per pass) and the depth-2
@@ -750,7 +805,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="metric",
-                    choices=["metric", "batched", "adjoint", "refine", "pipelined", "compressed", "lbm"])
+                    choices=["metric", "batched", "adjoint", "refine", "pipelined", "compressed", "lbm",
+                             "fp32"])
     ap.add_argument("--autotune", action="store_true",
                     help="let the library's autotuner pick the blocking first")
     ap.add_argument("--tmax", type=int, default=8, help="deepest blocking depth the autotuner tries")
@@ -788,7 +844,7 @@ def main():
     ensure_built()
     fn = {"metric": bench_metric, "batched": bench_batched, "adjoint": bench_adjoint,
           "refine": bench_refine, "pipelined": bench_pipelined,
-          "compressed": bench_compressed, "lbm": bench_lbm}[args.workload]
+          "compressed": bench_compressed, "lbm": bench_lbm, "fp32": bench_fp32}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 
