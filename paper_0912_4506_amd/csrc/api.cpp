@@ -435,7 +435,8 @@ const MeasuredShape kMeasured[] = {
     {JAC_F64, KIND_PLAIN, 5, 64, 60, 12}, {JAC_F64, KIND_PLAIN, 6, 64, 48, 8},
     {JAC_F32, KIND_PLAIN, 4, 64, 72, 12}, {JAC_F32, KIND_PLAIN, 5, 64, 80, 16},
     {JAC_F32, KIND_PLAIN, 6, 64, 80, 16}, {JAC_F32, KIND_PLAIN, 7, 64, 80, 16},
-    {JAC_F32, KIND_PLAIN, 8, 64, 80, 16}, {JAC_F32, KIND_RHS, 4, 64, 56, 8},
+    {JAC_F32, KIND_PLAIN, 8, 64, 80, 16}, {JAC_F32, KIND_RHS, 2, 64, 80, 16},
+    {JAC_F32, KIND_RHS, 3, 64, 80, 16},   {JAC_F32, KIND_RHS, 4, 64, 56, 8},
     {JAC_F32, KIND_RHS, 5, 64, 60, 12},   {JAC_F32, KIND_RHS, 6, 64, 60, 12},
     {JAC_F32, KIND_RHS, 7, 64, 64, 16},   {JAC_F32, KIND_RHS, 8, 64, 64, 16},
     // adjoint passes (trace mode), timed at 256^3, T = 32

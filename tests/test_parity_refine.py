@@ -143,9 +143,10 @@ def test_fill_dense_and_strided(jac, dtype):
     assert torch.all(base[:, :, 7:] == 1.0).item()
 
 
-@pytest.mark.parametrize("dtype,t", [(torch.float64, 4), (torch.float64, 8), (torch.float32, 4),
-                                     (torch.float32, 5), (torch.float32, 6), (torch.float32, 7),
-                                     (torch.float32, 8)])
+@pytest.mark.parametrize("dtype,t", [(torch.float64, 2), (torch.float64, 3), (torch.float64, 4),
+                                     (torch.float64, 8), (torch.float32, 2), (torch.float32, 3),
+                                     (torch.float32, 4), (torch.float32, 5), (torch.float32, 6),
+                                     (torch.float32, 7), (torch.float32, 8)])
 def test_rhs_sweeps(jac, dtype, t):
     """jacobi_tblock with rhs from e = 0: FP64 bitwise with the oracle's
     right-hand-side sweeps; FP32 within 1e-5 of max|e|."""
